@@ -1,0 +1,184 @@
+/*
+ * srp.h - C ABI of libsrp: steered response power (SRP) maps on one AMD
+ * Instinct MI355X (gfx950), conventional and with the Nyquist-Shannon
+ * approximation of Dietzen, De Sena and van Waterschoot, "Low-Complexity
+ * Steered Response Power Mapping based on Nyquist-Shannon Sampling"
+ * (WASPAA 2021).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Pointers are DEVICE pointers unless marked "host". Device buffers are
+ *   owned by the caller, contiguous, and 16-byte aligned; the library never
+ *   frees them.
+ * - `stream` is a hipStream_t (NULL = the default stream). Every call that
+ *   takes a stream validates its arguments on the host, then enqueues its
+ *   kernels on that stream and returns before they finish. An invalid
+ *   argument returns SRP_ERR_INVALID_ARG with nothing enqueued and no output
+ *   written. A failed launch returns SRP_ERR_DEVICE. No call aborts the
+ *   process or throws; srp_last_error() gives the message of the last failing
+ *   call on the calling thread.
+ * - Microphones are 0-based. Pair p of microphones (m, m') with m > m' has
+ *   index p = m(m-1)/2 + m' (the pair set of Section 2.1); P = M(M-1)/2.
+ * - Frequency bins: f_k = k fs / L for k = 0 .. K-1, K = floor(f_max L / fs) + 1.
+ *   Bin weights w_k = 1 at k = 0 and at f_k = fs/2, 2 elsewhere: the
+ *   one-sided sum that stands for the integral over [-omega_0, omega_0]
+ *   (Eq. SRP_T).
+ * - Discrete GCC: xi_p(tau) = sum_k w_k Re[psi_p(k) exp(j 2 pi f_k tau)]
+ *   (Eq. GCC_IFT with the integral replaced by a sum, Section 2.4).
+ * - Critical period T = 1 / (2 f_max) (Section 3.1). Per-pair window
+ *   half-width h_p = N_p + N_aux with N_p = floor(d_p / (c T)) evaluated in
+ *   float64 exactly in that order, d_p = ||p_m - p_m'||; the window holds
+ *   W_p = 2 h_p + 1 lags n = -h_p .. h_p (Eq. SRPapprox, Section 3.3).
+ * - Packed GCC samples: sample (p, n) of a frame sits at column
+ *   offset_p + (n + h_p), offset_0 = 0, offset_{p+1} = offset_p + W_p,
+ *   S = offset_P.
+ */
+#ifndef SRP_H
+#define SRP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SRP_OK = 0,
+  SRP_ERR_INVALID_ARG = -1,
+  SRP_ERR_OUT_OF_MEMORY = -2,
+  SRP_ERR_DEVICE = -3,
+  SRP_ERR_UNSUPPORTED = -4
+} srp_status;
+
+/* Arithmetic type of a map or sample kernel's contraction. Accumulation is
+ * float32 for SRP_FP32/SRP_BF16/SRP_FP16 (matrix cores) and float64 for
+ * SRP_FP64 (vector units; a slow exactness check, not a fast path). */
+typedef enum { SRP_FP32 = 0, SRP_BF16 = 1, SRP_FP16 = 2, SRP_FP64 = 3 } srp_dtype;
+
+/* Propagation model: near field (Eq. Deltat_i, candidates are points in
+ * metres) or far field (Eq. Deltat_i_spher, candidates are unit incident
+ * directions r pointing from the source towards the array). */
+typedef enum { SRP_NEAR_FIELD = 0, SRP_FAR_FIELD = 1 } srp_field;
+
+/* Analysis window applied to every frame before its DFT: periodic Hann
+ * 0.5 - 0.5 cos(2 pi t / L), its square root, or rectangular. */
+typedef enum { SRP_WIN_HANN = 0, SRP_WIN_SQRT_HANN = 1, SRP_WIN_RECT = 2 } srp_window;
+
+/* Weighting of the GCC matrix (Eq. corrmatrix). Only the phase transform. */
+typedef enum { SRP_PHAT = 0 } srp_weighting;
+
+/* Per-frame map maximum (Section 2.2: the location estimate is the argmax).
+ * Ties go to the lowest candidate index. 16 bytes. */
+typedef struct {
+  int64_t index;
+  float value;
+  int32_t reserved;
+} srp_peak;
+
+/* Opaque, immutable array description. Owns device copies of the geometry
+ * and the tables derived from it. May be used from several streams at once;
+ * the caller keeps it alive until all work enqueued with it has finished. */
+typedef struct srp_geometry_s srp_geometry_t;
+
+/* Layout summary of a geometry handle (all host values). */
+typedef struct {
+  int32_t M, P, L, K;      /* mics, pairs, frame length, one-sided bins            */
+  int64_t J;               /* candidates                                            */
+  int64_t S;               /* packed GCC samples per frame                          */
+  int32_t h_max;           /* max_p h_p                                             */
+  int32_t n_aux;
+  int32_t field, window;
+  double c, fs, f_max, T;  /* speed of sound, sample rate, band limit, period      */
+} srp_geometry_info;
+
+/* Host-only pair layout (Section 3.2, 3.3): computes h_p - n_aux = N_p for
+ * every pair (into N_p, P entries, may be NULL), the packed offsets (P + 1
+ * entries, may be NULL) and S (may be NULL). mic_xyz: host, M x 3 float64,
+ * metres, row-major. Requires M >= 2, c > 0, f_max > 0, n_aux >= 0. Touches
+ * no device. */
+srp_status srp_pair_layout(const double* mic_xyz, int32_t M, double c, double f_max,
+                           int32_t n_aux, int32_t* N_p, int64_t* offsets, int64_t* S);
+
+/* Creates a geometry handle (Section 2.1: microphone positions p_m, candidate
+ * locations q_i or directions r_i, speed of sound c, band limit omega_0).
+ *   mic_xyz   host, M x 3 float64 (metres)
+ *   cand_xyz  host, J x 3 float64: points (near field) or unit vectors (far field)
+ *   f_max     band limit omega_0 / (2 pi), 0 < f_max <= fs / 2
+ *   L         frame length, a power of two with 16 <= L <= 8192
+ *   n_aux     auxiliary samples per side, >= 0
+ * Invalid: M < 2 or M > 256, J < 1 or J >= 2^31, c <= 0, fs <= 0, bad L or
+ * f_max, n_aux < 0, 2 h_p + 1 > L for some pair, a far-field direction whose
+ * norm differs from 1 by more than 1e-9, a NULL pointer. Copies the tables to
+ * the device on `stream` and waits for the copies before returning, so the
+ * host arrays may be freed at once. */
+srp_status srp_geometry(const double* mic_xyz, int32_t M, const double* cand_xyz, int64_t J,
+                        int32_t field, double c, double fs, int32_t L, double f_max,
+                        int32_t n_aux, int32_t window, void* stream, srp_geometry_t** out);
+
+/* Layout of a handle; N_p (P entries) and offsets (P + 1) are host and may be NULL. */
+srp_status srp_geometry_query(const srp_geometry_t* g, srp_geometry_info* info, int32_t* N_p,
+                              int64_t* offsets);
+
+/* Frees the handle's device memory. The caller synchronises first. NULL is a no-op. */
+void srp_geometry_destroy(srp_geometry_t* g);
+
+/* Bytes of device workspace srp_cross_spectra needs for F frames (F * M * K * 8). */
+srp_status srp_cross_spectra_workspace(const srp_geometry_t* g, int32_t F, size_t* bytes);
+
+/* Frequency-domain GCC of every pair (Eq. corrmatrix with the PHAT weight):
+ * windowed DFT of each frame and microphone, then
+ * psi_p(k) = y_m y_m'^* / |y_m y_m'^*|, with psi_p(k) = 0 where y_m or y_m' is 0.
+ *   frames     device, F x M x L float32
+ *   workspace  device, >= srp_cross_spectra_workspace bytes (overwritten)
+ *   psi        device, F x P x K complex (interleaved float32 re, im), written
+ * F >= 1. */
+srp_status srp_cross_spectra(const srp_geometry_t* g, const float* frames, int32_t F,
+                             int32_t weighting, void* workspace, size_t workspace_bytes,
+                             float* psi, void* stream);
+
+/* GCC samples at the critical lags (Section 3.2, first step; cost Eq.
+ * SRPapproxcompC): xi[f][offset_p + n + h_p] = xi_p(n T) for |n| <= h_p.
+ *   psi  device, F x P x K complex64 as written by srp_cross_spectra
+ *   xi   device, F x S float32, written
+ * dtype: SRP_FP32 (the only type for this call). */
+srp_status srp_gcc_samples(const srp_geometry_t* g, const float* psi, int32_t F, int32_t dtype,
+                           float* xi, void* stream);
+
+/* Conventional SRP map (Eq. SRP_T_IFT with one discrete IFT per candidate,
+ * pair and bin, Section 2.4): map[f][i] = 2 sum_p xi_p(dt_p(i)).
+ *   psi    device, F x P x K complex64
+ *   map    device, F x J float32, written; may be NULL if peaks is not
+ *   peaks  device, F srp_peak, written; may be NULL if map is not
+ * dtype: SRP_FP32, SRP_BF16, SRP_FP16 or SRP_FP64 (see srp_dtype). */
+srp_status srp_map_conventional(const srp_geometry_t* g, const float* psi, int32_t F,
+                                int32_t dtype, float* map, srp_peak* peaks, void* stream);
+
+/* Nyquist-Shannon SRP approximation (Eq. SRPapprox summed over pairs as in
+ * Eq. SRP_T_IFT; cost Eq. SRPapproxcompR):
+ * map[f][i] = 2 sum_p sum_{|n| <= h_p} xi_p(nT) sinc(dt_p(i) / T - n),
+ * sinc(x) = sin(pi x) / (pi x), sinc(0) = 1. TDOAs are formed on the fly in
+ * float64; sinc weights are formed from the float64 argument split into an
+ * integer and a float32 fraction.
+ *   xi     device, F x S float32 (srp_gcc_samples layout)
+ *   map    device, F x J float32, written; may be NULL if peaks is not
+ *   peaks  device, F srp_peak, written; may be NULL if map is not
+ * dtype: SRP_FP32, SRP_BF16, SRP_FP16 or SRP_FP64. */
+srp_status srp_map_nyquist(const srp_geometry_t* g, const float* xi, int32_t F, int32_t dtype,
+                           float* map, srp_peak* peaks, void* stream);
+
+/* Per-frame argmax of a map (Section 2.2), lowest index on ties.
+ *   map    device, F x J float32;  peaks device, F srp_peak, written.
+ * F >= 1, 1 <= J < 2^31. */
+srp_status srp_argmax(const float* map, int32_t F, int64_t J, srp_peak* peaks, void* stream);
+
+/* Message of the last non-OK status returned on this thread ("" if none). */
+const char* srp_last_error(void);
+
+/* Library version string. */
+const char* srp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SRP_H */

@@ -92,7 +92,13 @@ def pair_windows(mic_xyz, c: float, f_max: float, n_aux: int):
     mic = np.asarray(mic_xyz, dtype=np.float64)
     T = critical_period(f_max)
     pairs = pair_list(mic.shape[0])
-    d = np.array([np.linalg.norm(mic[m] - mic[mp]) for m, mp in pairs])
+    def dist(a, b):
+        # x, y, z summed in that order in float64, so floor() resolves an exact
+        # tie the same way wherever this reading is implemented
+        dx, dy, dz = float(a[0] - b[0]), float(a[1] - b[1]), float(a[2] - b[2])
+        return math.sqrt(dx * dx + dy * dy + dz * dz)
+
+    d = np.array([dist(mic[m], mic[mp]) for m, mp in pairs])
     N = np.array([int(math.floor(dp / (c * T))) for dp in d], dtype=np.int64)
     W = 2 * N + 2 * n_aux + 1
     offsets = np.zeros(len(pairs) + 1, dtype=np.int64)

@@ -1,0 +1,10 @@
+"""MI355X-native steered response power (SRP) maps: conventional SRP-PHAT and the
+Nyquist-Shannon approximation of Dietzen, De Sena and van Waterschoot (WASPAA 2021).
+
+All computation runs in libsrp.so (hand-written HIP kernels for gfx950,
+include/srp.h); this package is its thin Python binding plus a frame
+pipeline helper.
+"""
+from ._lib import (DTYPES, EXPORTS, Geometry, SrpError, argmax, cross_spectra, decode_peaks,  # noqa: F401
+                   gcc_samples, lib, map_conventional, map_nyquist, pair_layout, version)
+from .pipeline import SrpPipeline  # noqa: F401

@@ -1,0 +1,267 @@
+"""ctypes binding of libsrp (include/srp.h).
+
+Argument marshalling only: every step of the SRP path runs in the library's
+HIP kernels. PyTorch supplies device memory and the current stream. There is
+no CPU fallback: if libsrp.so is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsrp.so")
+
+SRP_OK, SRP_ERR_INVALID_ARG, SRP_ERR_OUT_OF_MEMORY, SRP_ERR_DEVICE, SRP_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
+DTYPES = {"fp32": 0, "bf16": 1, "fp16": 2, "fp64": 3}
+FIELDS = {"near": 0, "far": 1}
+WINDOWS = {"hann": 0, "sqrt_hann": 1, "rect": 2}
+PHAT = 0
+
+# exported symbols of include/srp.h
+EXPORTS = ("srp_pair_layout", "srp_geometry", "srp_geometry_query", "srp_geometry_destroy",
+           "srp_cross_spectra_workspace", "srp_cross_spectra", "srp_gcc_samples",
+           "srp_map_conventional", "srp_map_nyquist", "srp_argmax", "srp_last_error",
+           "srp_version")
+
+
+class SrpError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libsrp status {status}: {msg}")
+        self.status = status
+
+
+class GeometryInfo(C.Structure):
+    _fields_ = [("M", C.c_int32), ("P", C.c_int32), ("L", C.c_int32), ("K", C.c_int32),
+                ("J", C.c_int64), ("S", C.c_int64), ("h_max", C.c_int32), ("n_aux", C.c_int32),
+                ("field", C.c_int32), ("window", C.c_int32), ("c", C.c_double),
+                ("fs", C.c_double), ("f_max", C.c_double), ("T", C.c_double)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Loads libsrp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2012_09499_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    L.srp_pair_layout.argtypes = [vp, i32, dbl, dbl, i32, vp, vp, vp]
+    L.srp_geometry.argtypes = [vp, i32, vp, i64, i32, dbl, dbl, i32, dbl, i32, i32, vp,
+                               C.POINTER(vp)]
+    L.srp_geometry_query.argtypes = [vp, C.POINTER(GeometryInfo), vp, vp]
+    L.srp_geometry_destroy.argtypes = [vp]
+    L.srp_geometry_destroy.restype = None
+    L.srp_cross_spectra_workspace.argtypes = [vp, i32, C.POINTER(C.c_size_t)]
+    L.srp_cross_spectra.argtypes = [vp, vp, i32, i32, vp, C.c_size_t, vp, vp]
+    L.srp_gcc_samples.argtypes = [vp, vp, i32, i32, vp, vp]
+    L.srp_map_conventional.argtypes = [vp, vp, i32, i32, vp, vp, vp]
+    L.srp_map_nyquist.argtypes = [vp, vp, i32, i32, vp, vp, vp]
+    L.srp_argmax.argtypes = [vp, i32, i64, vp, vp]
+    L.srp_last_error.restype = C.c_char_p
+    L.srp_last_error.argtypes = []
+    L.srp_version.restype = C.c_char_p
+    L.srp_version.argtypes = []
+    for name in EXPORTS:
+        if name not in ("srp_geometry_destroy", "srp_last_error", "srp_version"):
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(status: int) -> None:
+    if status != SRP_OK:
+        raise SrpError(status, lib().srp_last_error().decode())
+
+
+def version() -> str:
+    return lib().srp_version().decode()
+
+
+def _stream_handle(stream=None) -> int:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+def pair_layout(mic_xyz, c: float, f_max: float, n_aux: int):
+    """Host-only N_p, packed offsets and S (no device work)."""
+    mic = np.ascontiguousarray(mic_xyz, dtype=np.float64)
+    M = mic.shape[0]
+    P = M * (M - 1) // 2
+    N_p = np.zeros(max(P, 1), dtype=np.int32)
+    off = np.zeros(P + 1, dtype=np.int64)
+    S = C.c_int64(0)
+    _check(lib().srp_pair_layout(mic.ctypes.data, M, float(c), float(f_max), int(n_aux),
+                                 N_p.ctypes.data, off.ctypes.data, C.addressof(S)))
+    return N_p[:P], off, int(S.value)
+
+
+def _need_cuda(t, name, dtype=None, shape=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+class Geometry:
+    """Device-resident array geometry (srp_geometry)."""
+
+    def __init__(self, mic_xyz, candidates, *, fs: float, L: int, c: float = 343.0,
+                 f_max: Optional[float] = None, n_aux: int = 2, field: str = "near",
+                 window: str = "hann", stream=None):
+        mic = np.ascontiguousarray(mic_xyz, dtype=np.float64)
+        cand = np.ascontiguousarray(candidates, dtype=np.float64).reshape(-1, 3)
+        f_max = fs / 2.0 if f_max is None else f_max
+        h = C.c_void_p()
+        _check(lib().srp_geometry(mic.ctypes.data, mic.shape[0], cand.ctypes.data,
+                                  cand.shape[0], FIELDS[field], float(c), float(fs), int(L),
+                                  float(f_max), int(n_aux), WINDOWS[window],
+                                  _stream_handle(stream), C.byref(h)))
+        self._h = h
+        info = GeometryInfo()
+        P = mic.shape[0] * (mic.shape[0] - 1) // 2
+        self.N_p = np.zeros(P, dtype=np.int32)
+        self.offsets = np.zeros(P + 1, dtype=np.int64)
+        _check(lib().srp_geometry_query(h, C.byref(info), self.N_p.ctypes.data,
+                                        self.offsets.ctypes.data))
+        self.info = info
+        self.M, self.P, self.L, self.K = info.M, info.P, info.L, info.K
+        self.J, self.S, self.h_max, self.n_aux = info.J, info.S, info.h_max, info.n_aux
+        self.fs, self.c, self.f_max, self.T = info.fs, info.c, info.f_max, info.T
+        self.field = field
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("geometry closed")
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().srp_geometry_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self, F: int) -> int:
+        n = C.c_size_t(0)
+        _check(lib().srp_cross_spectra_workspace(self.handle, int(F), C.byref(n)))
+        return int(n.value)
+
+
+def cross_spectra(g: Geometry, frames, out=None, workspace=None, stream=None):
+    """frames [F][M][L] float32 -> psi [F][P][K] complex64 (srp_cross_spectra)."""
+    import torch
+    _need_cuda(frames, "frames", torch.float32)
+    F = frames.shape[0]
+    if frames.dim() != 3 or frames.shape[1] != g.M or frames.shape[2] != g.L:
+        raise ValueError(f"frames must be [F][{g.M}][{g.L}]")
+    nbytes = g.workspace_bytes(F)
+    if workspace is None:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=frames.device)
+    if out is None:
+        out = torch.empty((F, g.P, g.K), dtype=torch.complex64, device=frames.device)
+    _need_cuda(out, "psi", torch.complex64, (F, g.P, g.K))
+    _check(lib().srp_cross_spectra(g.handle, frames.data_ptr(), F, PHAT, workspace.data_ptr(),
+                                   workspace.numel() * workspace.element_size(), out.data_ptr(),
+                                   _stream_handle(stream)))
+    return out
+
+
+def gcc_samples(g: Geometry, psi, out=None, dtype: str = "fp32", stream=None):
+    """psi [F][P][K] complex64 -> xi [F][S] float32 (srp_gcc_samples)."""
+    import torch
+    _need_cuda(psi, "psi", torch.complex64)
+    F = psi.shape[0]
+    if out is None:
+        out = torch.empty((F, g.S), dtype=torch.float32, device=psi.device)
+    _need_cuda(out, "xi", torch.float32, (F, g.S))
+    _check(lib().srp_gcc_samples(g.handle, psi.data_ptr(), F, DTYPES[dtype], out.data_ptr(),
+                                 _stream_handle(stream)))
+    return out
+
+
+def _map_outputs(g, F, device, want_map, want_peaks, map_out, peaks_out):
+    import torch
+    m = map_out
+    if m is None and want_map:
+        m = torch.empty((F, g.J), dtype=torch.float32, device=device)
+    if m is not None:
+        _need_cuda(m, "map", torch.float32, (F, g.J))
+    pk = peaks_out
+    if pk is None and want_peaks:
+        pk = torch.empty((F, 2), dtype=torch.int64, device=device)
+    if pk is not None:
+        _need_cuda(pk, "peaks", torch.int64, (F, 2))
+    return m, pk
+
+
+def map_nyquist(g: Geometry, xi, dtype: str = "fp32", want_map: bool = True,
+                want_peaks: bool = True, map_out=None, peaks_out=None, stream=None):
+    """xi [F][S] -> (map [F][J] float32 | None, peaks [F][2] int64 | None) (srp_map_nyquist)."""
+    import torch
+    _need_cuda(xi, "xi", torch.float32)
+    F = xi.shape[0]
+    if xi.shape[1] != g.S:
+        raise ValueError(f"xi must be [F][{g.S}]")
+    m, pk = _map_outputs(g, F, xi.device, want_map, want_peaks, map_out, peaks_out)
+    _check(lib().srp_map_nyquist(g.handle, xi.data_ptr(), F, DTYPES[dtype],
+                                 m.data_ptr() if m is not None else None,
+                                 pk.data_ptr() if pk is not None else None,
+                                 _stream_handle(stream)))
+    return m, pk
+
+
+def map_conventional(g: Geometry, psi, dtype: str = "fp32", want_map: bool = True,
+                     want_peaks: bool = True, map_out=None, peaks_out=None, stream=None):
+    """psi [F][P][K] complex64 -> (map, peaks) (srp_map_conventional)."""
+    import torch
+    _need_cuda(psi, "psi", torch.complex64)
+    F = psi.shape[0]
+    if tuple(psi.shape[1:]) != (g.P, g.K):
+        raise ValueError(f"psi must be [F][{g.P}][{g.K}]")
+    m, pk = _map_outputs(g, F, psi.device, want_map, want_peaks, map_out, peaks_out)
+    _check(lib().srp_map_conventional(g.handle, psi.data_ptr(), F, DTYPES[dtype],
+                                      m.data_ptr() if m is not None else None,
+                                      pk.data_ptr() if pk is not None else None,
+                                      _stream_handle(stream)))
+    return m, pk
+
+
+def argmax(srp_map, peaks_out=None, stream=None):
+    """map [F][J] float32 -> peaks [F][2] int64 (srp_argmax)."""
+    import torch
+    _need_cuda(srp_map, "map", torch.float32)
+    F, J = srp_map.shape
+    pk = peaks_out
+    if pk is None:
+        pk = torch.empty((F, 2), dtype=torch.int64, device=srp_map.device)
+    _need_cuda(pk, "peaks", torch.int64, (F, 2))
+    _check(lib().srp_argmax(srp_map.data_ptr(), F, J, pk.data_ptr(), _stream_handle(stream)))
+    return pk
+
+
+def decode_peaks(peaks) -> Tuple[np.ndarray, np.ndarray]:
+    """srp_peak records [F][2] int64 -> (index int64 [F], value float32 [F]) on the host."""
+    h = peaks.detach().cpu().contiguous().numpy()
+    idx = h[:, 0].copy()
+    val = h.view(np.int32)[:, 2].copy().view(np.float32)
+    return idx, val

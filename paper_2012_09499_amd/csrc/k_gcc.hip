@@ -1,0 +1,99 @@
+// GCC samples at the critical lags (Section 3.2, first step; cost Eq.
+// SRPapproxcompC): xi_p(n T) = sum_k w_k Re[psi_p(k) exp(j 2 pi f_k n T)]
+// for |n| <= h_p.
+//
+// For one pair this is a dense product: rows = frames, inner = 2K (the real
+// and imaginary part of each bin), columns = the pair's lags:
+//   xi[f][t] = sum_k  (w_k Re psi[f][k]) cos(theta_kt) + (w_k Im psi[f][k]) (-sin(theta_kt)).
+// One wave computes a 32-lag tile of one pair for 32 * FT frames with the
+// float32 matrix-core instruction v_mfma_f32_32x32x2f32: each step consumes
+// one bin (k2 = 0: real part, k2 = 1: imaginary part). The phase table holds
+// (cos, -sin) of 2 pi f_k n T, built in float64 on the host with the phase
+// reduced exactly mod 2 pi and rounded once.
+#include "srp_device.h"
+#include "srp_internal.h"
+
+namespace srp {
+namespace {
+
+template <int FT>
+__global__ __launch_bounds__(64) void gcc_samples_kernel(
+    const float2* __restrict__ psi, const float* __restrict__ binw,
+    const float2* __restrict__ table, int nw, int h_max, const LagRun* __restrict__ tiles,
+    const PairDesc* __restrict__ pairs, int F, int P, int K, int S, float* __restrict__ xi) {
+  const LagRun tl = tiles[blockIdx.x];
+  const PairDesc pd = pairs[tl.p];
+  const int lane = threadIdx.x;
+  const int cl = lane & 31;
+  const int g = lane >> 5;
+  const int fbase = blockIdx.y * 32 * FT;
+
+  // A operand: lane (cl, g) holds A[frame cl][k2 = g] = w_k (Re | Im) psi[f][p][k].
+  const float* arow[FT];
+#pragma unroll
+  for (int ft = 0; ft < FT; ++ft) {
+    int f = fbase + ft * 32 + cl;
+    f = f < F ? f : F - 1;
+    arow[ft] = reinterpret_cast<const float*>(psi + ((size_t)f * P + tl.p) * K) + g;
+  }
+  // B operand: lane (cl, g) holds B[k2 = g][lag cl] = (cos | -sin)(theta_k,n).
+  const float* brow = reinterpret_cast<const float*>(table + (h_max - pd.h + tl.t0 + cl)) + g;
+  const size_t bstride = 2 * (size_t)nw;
+
+  floatx16 acc[FT];
+#pragma unroll
+  for (int ft = 0; ft < FT; ++ft)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[ft][r] = 0.0f;
+
+  int k = 0;
+  for (; k + 4 <= K; k += 4) {
+    float b[4], a[4][FT];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      b[u] = brow[(size_t)(k + u) * bstride];
+      const float wk = binw[k + u];
+#pragma unroll
+      for (int ft = 0; ft < FT; ++ft) a[u][ft] = arow[ft][2 * (k + u)] * wk;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int ft = 0; ft < FT; ++ft)
+        acc[ft] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[u][ft], b[u], acc[ft], 0, 0, 0);
+  }
+  for (; k < K; ++k) {
+    const float b = brow[(size_t)k * bstride];
+    const float wk = binw[k];
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft)
+      acc[ft] = __builtin_amdgcn_mfma_f32_32x32x2f32(arow[ft][2 * k] * wk, b, acc[ft], 0, 0, 0);
+  }
+
+  // D[frame][lag]: lane (cl, g), register r holds frame 8 (r / 4) + 4 g + r % 4, lag cl.
+  if (cl < tl.len) {
+    float* col = xi + pd.off + tl.t0 + cl;
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int f = fbase + ft * 32 + 8 * (r >> 2) + 4 * g + (r & 3);
+        if (f < F) col[(size_t)f * S] = acc[ft][r];
+      }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_gcc_samples(const srp_geometry_s* g, const float2* psi, int F, float* xi,
+                              hipStream_t s) {
+  constexpr int FT = 2;
+  const int n_tiles = static_cast<int>(g->gcc_tiles.size());
+  dim3 grid(n_tiles, (F + 32 * FT - 1) / (32 * FT));
+  hipLaunchKernelGGL(gcc_samples_kernel<FT>, grid, dim3(64), 0, s, psi, g->d_binw,
+                     g->d_gcc_table, g->gcc_nw, g->info.h_max, g->d_gcc_tiles, g->d_pairs, F,
+                     g->info.P, g->info.K, static_cast<int>(g->info.S), xi);
+  return hipGetLastError();
+}
+
+}  // namespace srp

@@ -1,0 +1,281 @@
+// Nyquist-Shannon SRP approximation (Eq. SRPapprox summed over pairs as in
+// Eq. SRP_T_IFT; cost Eq. SRPapproxcompR):
+//   map[f][i] = 2 sum_p sum_{|n| <= h_p} xi_p(nT) sinc(x_p(i) - n),  x_p(i) = dt_p(i) / T.
+//
+// For a block of candidates and a block of frames this is a product of a
+// weight matrix [candidates x packed lags] with the samples [packed lags x
+// frames]. The weights are never stored: each lane forms them in registers
+// right before the matrix-core instruction that consumes them.
+//
+// Weight formation. With x = xi + xf (xi = rint(x) in float64, xf = x - xi
+// exact in float64, then rounded once to float32, |xf| <= 1/2):
+//   sinc(x - n) = (-1)^(xi - n) sin(pi xf) / (pi ((xi - n) + xf)).
+// (xi - n) is an exact small integer, so the denominator carries a single
+// float32 rounding; sin(pi xf) / pi is formed once per candidate and pair. At
+// xf = 0 the fraction is replaced by 1e-30, which gives weight 1 at n = xi and
+// 0 elsewhere (to float32 precision) without a branch per weight. |weight| <= 1.
+//
+// TDOAs: x = (||q - p_m|| - ||q - p_m'||) / (c T) in float64 (near field,
+// Eq. Deltat_i) or (p_m - p_m') . r / (c T) (far field, Eq. Deltat_i_spher),
+// recomputed per pair from the candidate held in registers, so no J x P table
+// exists anywhere.
+//
+// FP32 kernel layout (v_mfma_f32_32x32x2f32, D[frame][cand] += A[frame][k] B[k][cand]):
+//   block = 4 waves; each wave owns 32 * CT candidates, all waves share 32 * FT frames;
+//   step s of a lag run covers lags t = 2s (k = 0, lanes 0-31) and 2s + 1 (k = 1, lanes 32-63);
+//   A = samples staged in LDS as [frame][lag]; B = weights (lane = candidate);
+//   epilogue: x2, optional map store, argmax via LDS u64 max + one global atomic per frame.
+#include "srp_device.h"
+#include "srp_internal.h"
+
+namespace srp {
+namespace {
+
+constexpr int kStride = kNyqRunMax + 1;  // LDS row stride (odd) of the [frame][lag] tile
+
+struct NyqArgs {
+  const double* cand;      // [3][J]
+  const double* mic;       // [M][3]
+  const PairDesc* pairs;
+  const LagRun* runs;
+  int n_runs;
+  const float* xi;         // [F][S]
+  int F;
+  int S;
+  int64_t J;
+  double inv_cT;
+  int far_field;
+  float* map;              // [F][J] or null
+  unsigned long long* keys;  // peaks viewed as u64 pairs, or null
+};
+
+// x_p(i) = dt_p(i) / T for the candidate (qx, qy, qz), float64.
+__device__ __forceinline__ double pair_x(const NyqArgs& a, const PairDesc& pd, double qx,
+                                         double qy, double qz) {
+  const double* pm = a.mic + 3 * pd.m;
+  const double* pn = a.mic + 3 * pd.mp;
+  if (a.far_field) {
+    return ((pm[0] - pn[0]) * qx + (pm[1] - pn[1]) * qy + (pm[2] - pn[2]) * qz) * a.inv_cT;
+  }
+  const double ax = qx - pm[0], ay = qy - pm[1], az = qz - pm[2];
+  const double bx = qx - pn[0], by = qy - pn[1], bz = qz - pn[2];
+  return (sqrt(ax * ax + ay * ay + az * az) - sqrt(bx * bx + by * by + bz * bz)) * a.inv_cT;
+}
+
+template <int CT, int FT>
+__global__ __launch_bounds__(256) void nyquist_f32_kernel(NyqArgs a) {
+  constexpr int FB = 32 * FT;
+  constexpr int JW = 32 * CT;
+  constexpr int JB = 4 * JW;
+  __shared__ float xs[FB * kStride];
+  __shared__ unsigned long long kbest[FB];
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const int cl = lane & 31;
+  const int g = lane >> 5;
+  const int64_t jb = (int64_t)blockIdx.x * JB + wave * JW;
+  const int f0 = blockIdx.y * FB;
+
+  double qx[CT], qy[CT], qz[CT];
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+    int64_t ci = jb + ct * 32 + cl;
+    ci = ci < a.J ? ci : a.J - 1;
+    qx[ct] = a.cand[ci];
+    qy[ct] = a.cand[a.J + ci];
+    qz[ct] = a.cand[2 * a.J + ci];
+  }
+  for (int i = tid; i < FB; i += 256) kbest[i] = 0ull;
+
+  floatx16 acc[CT][FT];
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[ct][ft][r] = 0.0f;
+
+  for (int ri = 0; ri < a.n_runs; ++ri) {
+    const LagRun run = a.runs[ri];
+    const PairDesc pd = a.pairs[run.p];
+    const int len_pad = (run.len + 1) & ~1;
+    __syncthreads();
+    // stage samples [frame][lag] (zero past the run and past F)
+    const float* src = a.xi + pd.off + run.t0;
+    for (int f = wave; f < FB; f += 4) {
+      const int fg = f0 + f;
+      for (int t = lane; t < len_pad; t += 64) {
+        float v = 0.0f;
+        if (fg < a.F && t < run.len) v = src[(size_t)fg * a.S + t];
+        xs[f * kStride + t] = v;
+      }
+    }
+    __syncthreads();
+
+    float dnum[CT], frac[CT], qv[CT];
+    const int n_first = -pd.h + run.t0 + g;  // this lane's first lag in the run
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      const double x = pair_x(a, pd, qx[ct], qy[ct], qz[ct]);
+      const double xr = rint(x);
+      float xf = static_cast<float>(x - xr);
+      xf = fabsf(xf) < 1e-30f ? 1e-30f : xf;
+      const int ia = static_cast<int>(xr) - n_first;
+      const float sgn = (ia & 1) ? -1.0f : 1.0f;
+      qv[ct] = sgn * sinpif(xf) * 0.318309886183790671538f;
+      dnum[ct] = static_cast<float>(ia);
+      frac[ct] = xf;
+    }
+    const float* arow = xs + cl * kStride + g;
+    const int steps = len_pad >> 1;
+    for (int s = 0; s < steps; ++s) {
+      float w[CT];
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        w[ct] = qv[ct] * __builtin_amdgcn_rcpf(dnum[ct] + frac[ct]);
+        dnum[ct] -= 2.0f;
+      }
+      float av[FT];
+#pragma unroll
+      for (int ft = 0; ft < FT; ++ft) av[ft] = arow[ft * 32 * kStride + 2 * s];
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+        for (int ft = 0; ft < FT; ++ft)
+          acc[ct][ft] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[ft], w[ct], acc[ct][ft], 0, 0, 0);
+    }
+  }
+
+  // epilogue: D[frame][cand], lane (cl, g), register r -> frame 8 (r / 4) + 4 g + r % 4
+#pragma unroll
+  for (int ft = 0; ft < FT; ++ft) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int fl = ft * 32 + 8 * (r >> 2) + 4 * g + (r & 3);
+      const int fg = f0 + fl;
+      unsigned long long best = 0ull;
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        const int64_t ci = jb + ct * 32 + cl;
+        const float v = 2.0f * acc[ct][ft][r];
+        if (ci < a.J && fg < a.F) {
+          if (a.map) a.map[(size_t)fg * a.J + ci] = v;
+          const unsigned long long k = peak_key(v, static_cast<unsigned>(ci));
+          best = k > best ? k : best;
+        }
+      }
+      if (a.keys) {
+        best = half_wave_max(best);
+        if (cl == 0 && best) atomicMax(&kbest[fl], best);
+      }
+    }
+  }
+  if (a.keys) {
+    __syncthreads();
+    for (int i = tid; i < FB; i += 256) {
+      const unsigned long long k = kbest[i];
+      if (k && f0 + i < a.F) atomicMax(a.keys + 2 * (size_t)(f0 + i), k);
+    }
+  }
+}
+
+// Float64 instance (vector units): one thread per candidate, FB64 frames per
+// block. Same data flow as the FP32 kernel; exists to check indexing and
+// algebra against the float64 oracle to ~1e-12.
+constexpr int kFB64 = 8;
+
+__global__ __launch_bounds__(256) void nyquist_f64_kernel(NyqArgs a) {
+  __shared__ float xs[kFB64 * kStride];
+  __shared__ unsigned long long kbest[kFB64];
+  const int tid = threadIdx.x;
+  const int64_t ci0 = (int64_t)blockIdx.x * 256 + tid;
+  const int64_t ci = ci0 < a.J ? ci0 : a.J - 1;
+  const int f0 = blockIdx.y * kFB64;
+  const double qx = a.cand[ci], qy = a.cand[a.J + ci], qz = a.cand[2 * a.J + ci];
+  if (tid < kFB64) kbest[tid] = 0ull;
+  double acc[kFB64];
+#pragma unroll
+  for (int f = 0; f < kFB64; ++f) acc[f] = 0.0;
+  for (int ri = 0; ri < a.n_runs; ++ri) {
+    const LagRun run = a.runs[ri];
+    const PairDesc pd = a.pairs[run.p];
+    __syncthreads();
+    const float* src = a.xi + pd.off + run.t0;
+    for (int e = tid; e < kFB64 * run.len; e += 256) {
+      const int f = e / run.len, t = e - f * run.len;
+      const int fg = f0 + f;
+      xs[f * kStride + t] = fg < a.F ? src[(size_t)fg * a.S + t] : 0.0f;
+    }
+    __syncthreads();
+    const double x = pair_x(a, pd, qx, qy, qz);
+    const double xr = rint(x);
+    const double xf = x - xr;
+    const double sp = sinpi(xf);
+    for (int t = 0; t < run.len; ++t) {
+      const int n = -pd.h + run.t0 + t;
+      const int ia = static_cast<int>(xr) - n;
+      double wgt;
+      if (ia == 0 && xf == 0.0) {
+        wgt = 1.0;
+      } else {
+        wgt = ((ia & 1) ? -sp : sp) / (M_PI * (static_cast<double>(ia) + xf));
+      }
+#pragma unroll
+      for (int f = 0; f < kFB64; ++f) acc[f] += wgt * static_cast<double>(xs[f * kStride + t]);
+    }
+  }
+  for (int f = 0; f < kFB64; ++f) {
+    const int fg = f0 + f;
+    const float v = static_cast<float>(2.0 * acc[f]);
+    unsigned long long k = 0ull;
+    if (ci0 < a.J && fg < a.F) {
+      if (a.map) a.map[(size_t)fg * a.J + ci0] = v;
+      k = peak_key(v, static_cast<unsigned>(ci0));
+    }
+    if (a.keys) {
+      k = wave_max(k);
+      if ((tid & 63) == 0 && k) atomicMax(&kbest[f], k);
+    }
+  }
+  if (a.keys) {
+    __syncthreads();
+    if (tid < kFB64 && f0 + tid < a.F && kbest[tid]) atomicMax(a.keys + 2 * (size_t)(f0 + tid), kbest[tid]);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_nyquist(const srp_geometry_s* g, const float* xi, int F, int dtype, float* map,
+                          unsigned long long* keys, hipStream_t s) {
+  NyqArgs a;
+  a.cand = g->d_cand;
+  a.mic = g->d_mic;
+  a.pairs = g->d_pairs;
+  a.runs = g->d_nyq_runs;
+  a.n_runs = static_cast<int>(g->nyq_runs.size());
+  a.xi = xi;
+  a.F = F;
+  a.S = static_cast<int>(g->info.S);
+  a.J = g->info.J;
+  a.inv_cT = g->inv_cT;
+  a.far_field = g->info.field == SRP_FAR_FIELD;
+  a.map = map;
+  a.keys = keys;
+  if (dtype == SRP_FP32) {
+    constexpr int CT = 2, FT = 2;
+    constexpr int JB = 4 * 32 * CT, FB = 32 * FT;
+    dim3 grid(static_cast<unsigned>((a.J + JB - 1) / JB), (F + FB - 1) / FB);
+    hipLaunchKernelGGL((nyquist_f32_kernel<CT, FT>), grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
+  if (dtype == SRP_FP64) {
+    dim3 grid(static_cast<unsigned>((a.J + 255) / 256), (F + kFB64 - 1) / kFB64);
+    hipLaunchKernelGGL(nyquist_f64_kernel, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
+  return hipErrorNotSupported;
+}
+
+}  // namespace srp

@@ -1,0 +1,389 @@
+// C ABI of libsrp: argument validation, host-side geometry precompute and
+// kernel dispatch. Host arithmetic here is float64 and is compiled without
+// floating-point contraction, so pair distances and N_p = floor(d_p / (c T))
+// are reproducible bit for bit.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "srp_internal.h"
+
+namespace srp {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+namespace {
+
+srp_status fail(srp_status st, const std::string& msg) {
+  set_error(msg);
+  return st;
+}
+
+srp_status device_fail(hipError_t e, const char* where) {
+  return fail(SRP_ERR_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+// Makes the handle's device current for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
+    if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+  }
+  ~DeviceGuard() {
+    if (ok && prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Euclidean distance, summed x, y, z in that order (no contraction).
+double dist3(const double* a, const double* b) {
+  double dx = a[0] - b[0];
+  double dy = a[1] - b[1];
+  double dz = a[2] - b[2];
+  return std::sqrt(dx * dx + dy * dy + dz * dz);
+}
+
+// Per-pair window half-widths (Section 3.2): N_p = floor(d_p / (c T)).
+srp_status layout(const double* mic, int M, double c, double f_max, int n_aux,
+                  std::vector<int32_t>& N_p, std::vector<int64_t>& offsets) {
+  if (mic == nullptr) return fail(SRP_ERR_INVALID_ARG, "mic_xyz is NULL");
+  if (M < 2 || M > 256) return fail(SRP_ERR_INVALID_ARG, "M must be in [2, 256]");
+  if (!(c > 0.0) || !std::isfinite(c)) return fail(SRP_ERR_INVALID_ARG, "c must be > 0");
+  if (!(f_max > 0.0) || !std::isfinite(f_max))
+    return fail(SRP_ERR_INVALID_ARG, "f_max must be > 0");
+  if (n_aux < 0) return fail(SRP_ERR_INVALID_ARG, "n_aux must be >= 0");
+  for (int i = 0; i < 3 * M; ++i)
+    if (!std::isfinite(mic[i])) return fail(SRP_ERR_INVALID_ARG, "non-finite mic coordinate");
+  const double T = 1.0 / (2.0 * f_max);
+  const int P = M * (M - 1) / 2;
+  N_p.assign(P, 0);
+  offsets.assign(P + 1, 0);
+  int p = 0;
+  for (int m = 1; m < M; ++m) {
+    for (int mp = 0; mp < m; ++mp, ++p) {
+      const double d = dist3(mic + 3 * m, mic + 3 * mp);
+      const double q = std::floor(d / (c * T));
+      if (q > 1.0e8) return fail(SRP_ERR_INVALID_ARG, "pair window too long");
+      N_p[p] = static_cast<int32_t>(q);
+      offsets[p + 1] = offsets[p] + 2 * (int64_t)(N_p[p] + n_aux) + 1;
+    }
+  }
+  return SRP_OK;
+}
+
+template <typename T>
+hipError_t upload(T** dst, const T* src, size_t n, hipStream_t s) {
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), n * sizeof(T) > 0 ? n * sizeof(T) : 16);
+  if (e != hipSuccess) return e;
+  if (n == 0) return hipSuccess;
+  return hipMemcpyAsync(*dst, src, n * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+void free_geometry(srp_geometry_s* g) {
+  if (!g) return;
+  hipFree(g->d_mic);
+  hipFree(g->d_cand);
+  hipFree(g->d_pairs);
+  hipFree(g->d_gcc_tiles);
+  hipFree(g->d_nyq_runs);
+  hipFree(g->d_window);
+  hipFree(g->d_twiddle);
+  hipFree(g->d_gcc_table);
+  hipFree(g->d_binw);
+  delete g;
+}
+
+}  // namespace
+}  // namespace srp
+
+using namespace srp;
+
+extern "C" {
+
+const char* srp_last_error(void) { return g_last_error.c_str(); }
+
+const char* srp_version(void) { return "libsrp 0.1.0 gfx950"; }
+
+srp_status srp_pair_layout(const double* mic_xyz, int32_t M, double c, double f_max,
+                           int32_t n_aux, int32_t* N_p, int64_t* offsets, int64_t* S) {
+  std::vector<int32_t> np;
+  std::vector<int64_t> off;
+  srp_status st = layout(mic_xyz, M, c, f_max, n_aux, np, off);
+  if (st != SRP_OK) return st;
+  if (N_p) std::memcpy(N_p, np.data(), np.size() * sizeof(int32_t));
+  if (offsets) std::memcpy(offsets, off.data(), off.size() * sizeof(int64_t));
+  if (S) *S = off.back();
+  return SRP_OK;
+}
+
+srp_status srp_geometry(const double* mic_xyz, int32_t M, const double* cand_xyz, int64_t J,
+                        int32_t field, double c, double fs, int32_t L, double f_max,
+                        int32_t n_aux, int32_t window, void* stream, srp_geometry_t** out) {
+  if (out == nullptr) return fail(SRP_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (cand_xyz == nullptr) return fail(SRP_ERR_INVALID_ARG, "cand_xyz is NULL");
+  if (J < 1 || J >= (int64_t(1) << 31)) return fail(SRP_ERR_INVALID_ARG, "J must be in [1, 2^31)");
+  if (field != SRP_NEAR_FIELD && field != SRP_FAR_FIELD)
+    return fail(SRP_ERR_INVALID_ARG, "unknown field model");
+  if (window != SRP_WIN_HANN && window != SRP_WIN_SQRT_HANN && window != SRP_WIN_RECT)
+    return fail(SRP_ERR_INVALID_ARG, "unknown window");
+  if (!(fs > 0.0) || !std::isfinite(fs)) return fail(SRP_ERR_INVALID_ARG, "fs must be > 0");
+  if (!is_pow2(L) || L < 16 || L > 8192)
+    return fail(SRP_ERR_INVALID_ARG, "L must be a power of two in [16, 8192]");
+  if (!(f_max > 0.0) || f_max > fs / 2.0)
+    return fail(SRP_ERR_INVALID_ARG, "f_max must be in (0, fs/2]");
+  std::vector<int32_t> np;
+  std::vector<int64_t> off;
+  srp_status st = layout(mic_xyz, M, c, f_max, n_aux, np, off);
+  if (st != SRP_OK) return st;
+  const int P = M * (M - 1) / 2;
+  int h_max = 0;
+  for (int p = 0; p < P; ++p) {
+    const int h = np[p] + n_aux;
+    if (2 * (int64_t)h + 1 > L)
+      return fail(SRP_ERR_INVALID_ARG,
+                  "a pair window 2 (N_p + N_aux) + 1 exceeds L (the discrete GCC is L-periodic)");
+    h_max = h > h_max ? h : h_max;
+  }
+  if (off.back() >= (int64_t(1) << 31)) return fail(SRP_ERR_INVALID_ARG, "S too large");
+  for (int64_t i = 0; i < 3 * J; ++i)
+    if (!std::isfinite(cand_xyz[i]))
+      return fail(SRP_ERR_INVALID_ARG, "non-finite candidate coordinate");
+  if (field == SRP_FAR_FIELD) {
+    for (int64_t i = 0; i < J; ++i) {
+      const double* r = cand_xyz + 3 * i;
+      const double n = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+      if (std::fabs(n - 1.0) > 1e-9)
+        return fail(SRP_ERR_INVALID_ARG, "far-field candidates must be unit vectors");
+    }
+  }
+
+  srp_geometry_s* g = new (std::nothrow) srp_geometry_s();
+  if (!g) return fail(SRP_ERR_OUT_OF_MEMORY, "host allocation failed");
+  srp_geometry_info& in = g->info;
+  in.M = M;
+  in.P = P;
+  in.L = L;
+  in.K = static_cast<int32_t>(std::floor(f_max * L / fs)) + 1;
+  in.J = J;
+  in.S = off.back();
+  in.h_max = h_max;
+  in.n_aux = n_aux;
+  in.field = field;
+  in.window = window;
+  in.c = c;
+  in.fs = fs;
+  in.f_max = f_max;
+  in.T = 1.0 / (2.0 * f_max);
+  g->inv_cT = 1.0 / (c * in.T);
+  g->fs_over_c = fs / c;
+  g->log2L = 0;
+  while ((1 << g->log2L) < L) ++g->log2L;
+  g->N_p = np;
+  g->offsets = off;
+  g->pairs.resize(P);
+  {
+    int p = 0;
+    for (int m = 1; m < M; ++m)
+      for (int mp = 0; mp < m; ++mp, ++p)
+        g->pairs[p] = PairDesc{m, mp, np[p] + n_aux, static_cast<int32_t>(off[p])};
+  }
+  for (int p = 0; p < P; ++p) {
+    const int W = 2 * g->pairs[p].h + 1;
+    for (int t0 = 0; t0 < W; t0 += kGccLagTile)
+      g->gcc_tiles.push_back(LagRun{p, t0, W - t0 < kGccLagTile ? W - t0 : kGccLagTile, 0});
+    for (int t0 = 0; t0 < W; t0 += kNyqRunMax)
+      g->nyq_runs.push_back(LagRun{p, t0, W - t0 < kNyqRunMax ? W - t0 : kNyqRunMax, 0});
+  }
+  const int K = in.K;
+  g->gcc_nw = 2 * h_max + 1 + kGccLagTile;
+
+  // float64 tables, each rounded once to float32
+  std::vector<float> win(L);
+  for (int t = 0; t < L; ++t) {
+    const double hann = 0.5 - 0.5 * std::cos(2.0 * M_PI * t / L);
+    win[t] = static_cast<float>(window == SRP_WIN_HANN ? hann
+                                : window == SRP_WIN_SQRT_HANN ? std::sqrt(hann)
+                                                              : 1.0);
+  }
+  std::vector<float2> tw(L / 2);
+  for (int t = 0; t < L / 2; ++t) {
+    const double a = 2.0 * M_PI * t / L;
+    tw[t] = make_float2(static_cast<float>(std::cos(a)), static_cast<float>(-std::sin(a)));
+  }
+  std::vector<float> binw(K, 2.0f);
+  binw[0] = 1.0f;
+  if (2 * (K - 1) == L) binw[K - 1] = 1.0f;
+  // GCC phase 2 pi f_k n T in turns: k n fs T / L, reduced mod 1 exactly when
+  // fs T = 1/2 ... in general through the float64 fraction.
+  std::vector<float2> gtab((size_t)K * g->gcc_nw);
+  const bool integer_lags = (2.0 * f_max == fs);
+  for (int k = 0; k < K; ++k) {
+    for (int j = 0; j < g->gcc_nw; ++j) {
+      const int64_t n = (int64_t)j - h_max;
+      double turns;
+      if (integer_lags) {
+        int64_t r = ((int64_t)k * n) % L;
+        if (r < 0) r += L;
+        turns = (double)r / L;
+      } else {
+        const double v = (double)k * (double)n * (fs * in.T) / L;
+        turns = v - std::floor(v);
+      }
+      const double a = 2.0 * M_PI * turns;
+      gtab[(size_t)k * g->gcc_nw + j] =
+          make_float2(static_cast<float>(std::cos(a)), static_cast<float>(-std::sin(a)));
+    }
+  }
+  std::vector<double> cand_soa(3 * (size_t)J);
+  for (int64_t i = 0; i < J; ++i)
+    for (int d = 0; d < 3; ++d) cand_soa[(size_t)d * J + i] = cand_xyz[3 * i + d];
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipGetDevice(&g->device);
+  if (e == hipSuccess) e = upload(&g->d_mic, mic_xyz, 3 * (size_t)M, s);
+  if (e == hipSuccess) e = upload(&g->d_cand, cand_soa.data(), cand_soa.size(), s);
+  if (e == hipSuccess) e = upload(&g->d_pairs, g->pairs.data(), g->pairs.size(), s);
+  if (e == hipSuccess) e = upload(&g->d_gcc_tiles, g->gcc_tiles.data(), g->gcc_tiles.size(), s);
+  if (e == hipSuccess) e = upload(&g->d_nyq_runs, g->nyq_runs.data(), g->nyq_runs.size(), s);
+  if (e == hipSuccess) e = upload(&g->d_window, win.data(), win.size(), s);
+  if (e == hipSuccess) e = upload(&g->d_twiddle, tw.data(), tw.size(), s);
+  if (e == hipSuccess) e = upload(&g->d_gcc_table, gtab.data(), gtab.size(), s);
+  if (e == hipSuccess) e = upload(&g->d_binw, binw.data(), binw.size(), s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    const bool oom = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation);
+    std::string msg = std::string("srp_geometry: ") + hipGetErrorString(e);
+    free_geometry(g);
+    return fail(oom ? SRP_ERR_OUT_OF_MEMORY : SRP_ERR_DEVICE, msg);
+  }
+  *out = g;
+  return SRP_OK;
+}
+
+srp_status srp_geometry_query(const srp_geometry_t* g, srp_geometry_info* info, int32_t* N_p,
+                              int64_t* offsets) {
+  if (g == nullptr) return fail(SRP_ERR_INVALID_ARG, "geometry is NULL");
+  if (info) *info = g->info;
+  if (N_p) std::memcpy(N_p, g->N_p.data(), g->N_p.size() * sizeof(int32_t));
+  if (offsets) std::memcpy(offsets, g->offsets.data(), g->offsets.size() * sizeof(int64_t));
+  return SRP_OK;
+}
+
+void srp_geometry_destroy(srp_geometry_t* g) {
+  if (!g) return;
+  DeviceGuard dg(g->device);
+  free_geometry(g);
+}
+
+srp_status srp_cross_spectra_workspace(const srp_geometry_t* g, int32_t F, size_t* bytes) {
+  if (g == nullptr || bytes == nullptr) return fail(SRP_ERR_INVALID_ARG, "NULL argument");
+  if (F < 1) return fail(SRP_ERR_INVALID_ARG, "F must be >= 1");
+  *bytes = (size_t)F * g->info.M * g->info.K * sizeof(float2);
+  return SRP_OK;
+}
+
+srp_status srp_cross_spectra(const srp_geometry_t* g, const float* frames, int32_t F,
+                             int32_t weighting, void* workspace, size_t workspace_bytes,
+                             float* psi, void* stream) {
+  if (g == nullptr || frames == nullptr || workspace == nullptr || psi == nullptr)
+    return fail(SRP_ERR_INVALID_ARG, "srp_cross_spectra: NULL argument");
+  if (F < 1) return fail(SRP_ERR_INVALID_ARG, "F must be >= 1");
+  if (weighting != SRP_PHAT) return fail(SRP_ERR_UNSUPPORTED, "only PHAT weighting");
+  const size_t need = (size_t)F * g->info.M * g->info.K * sizeof(float2);
+  if (workspace_bytes < need) return fail(SRP_ERR_INVALID_ARG, "workspace too small");
+  DeviceGuard dg(g->device);
+  if (!dg.ok) return fail(SRP_ERR_DEVICE, "cannot select the geometry's device");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  float2* ytil = static_cast<float2*>(workspace);
+  hipError_t e = launch_fft_phat(g, frames, F, ytil, s);
+  if (e != hipSuccess) return device_fail(e, "fft_phat");
+  e = launch_cross(g, ytil, F, reinterpret_cast<float2*>(psi), s);
+  if (e != hipSuccess) return device_fail(e, "cross");
+  return SRP_OK;
+}
+
+srp_status srp_gcc_samples(const srp_geometry_t* g, const float* psi, int32_t F, int32_t dtype,
+                           float* xi, void* stream) {
+  if (g == nullptr || psi == nullptr || xi == nullptr)
+    return fail(SRP_ERR_INVALID_ARG, "srp_gcc_samples: NULL argument");
+  if (F < 1) return fail(SRP_ERR_INVALID_ARG, "F must be >= 1");
+  if (dtype != SRP_FP32) return fail(SRP_ERR_UNSUPPORTED, "srp_gcc_samples computes in FP32");
+  DeviceGuard dg(g->device);
+  if (!dg.ok) return fail(SRP_ERR_DEVICE, "cannot select the geometry's device");
+  hipError_t e = launch_gcc_samples(g, reinterpret_cast<const float2*>(psi), F, xi,
+                                    static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return device_fail(e, "gcc_samples");
+  return SRP_OK;
+}
+
+static srp_status check_map_args(const srp_geometry_t* g, const void* in, int32_t F,
+                                 int32_t dtype, float* map, srp_peak* peaks) {
+  if (g == nullptr || in == nullptr) return fail(SRP_ERR_INVALID_ARG, "NULL argument");
+  if (map == nullptr && peaks == nullptr)
+    return fail(SRP_ERR_INVALID_ARG, "map and peaks are both NULL");
+  if (F < 1) return fail(SRP_ERR_INVALID_ARG, "F must be >= 1");
+  if (dtype != SRP_FP32 && dtype != SRP_BF16 && dtype != SRP_FP16 && dtype != SRP_FP64)
+    return fail(SRP_ERR_INVALID_ARG, "unknown dtype");
+  return SRP_OK;
+}
+
+srp_status srp_map_nyquist(const srp_geometry_t* g, const float* xi, int32_t F, int32_t dtype,
+                           float* map, srp_peak* peaks, void* stream) {
+  srp_status st = check_map_args(g, xi, F, dtype, map, peaks);
+  if (st != SRP_OK) return st;
+  DeviceGuard dg(g->device);
+  if (!dg.ok) return fail(SRP_ERR_DEVICE, "cannot select the geometry's device");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipSuccess;
+  if (peaks) e = launch_peaks_init(peaks, F, s);
+  if (e == hipSuccess)
+    e = launch_nyquist(g, xi, F, dtype, map, reinterpret_cast<unsigned long long*>(peaks), s);
+  if (e == hipSuccess && peaks) e = launch_peaks_finalize(peaks, F, s);
+  if (e == hipErrorNotSupported) return fail(SRP_ERR_UNSUPPORTED, "dtype not supported here");
+  if (e != hipSuccess) return device_fail(e, "map_nyquist");
+  return SRP_OK;
+}
+
+srp_status srp_map_conventional(const srp_geometry_t* g, const float* psi, int32_t F,
+                                int32_t dtype, float* map, srp_peak* peaks, void* stream) {
+  srp_status st = check_map_args(g, psi, F, dtype, map, peaks);
+  if (st != SRP_OK) return st;
+  DeviceGuard dg(g->device);
+  if (!dg.ok) return fail(SRP_ERR_DEVICE, "cannot select the geometry's device");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipSuccess;
+  if (peaks) e = launch_peaks_init(peaks, F, s);
+  if (e == hipSuccess)
+    e = launch_conventional(g, reinterpret_cast<const float2*>(psi), F, dtype, map,
+                            reinterpret_cast<unsigned long long*>(peaks), s);
+  if (e == hipSuccess && peaks) e = launch_peaks_finalize(peaks, F, s);
+  if (e == hipErrorNotSupported) return fail(SRP_ERR_UNSUPPORTED, "dtype not supported here");
+  if (e != hipSuccess) return device_fail(e, "map_conventional");
+  return SRP_OK;
+}
+
+srp_status srp_argmax(const float* map, int32_t F, int64_t J, srp_peak* peaks, void* stream) {
+  if (map == nullptr || peaks == nullptr) return fail(SRP_ERR_INVALID_ARG, "NULL argument");
+  if (F < 1) return fail(SRP_ERR_INVALID_ARG, "F must be >= 1");
+  if (J < 1 || J >= (int64_t(1) << 31)) return fail(SRP_ERR_INVALID_ARG, "J must be in [1, 2^31)");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_peaks_init(peaks, F, s);
+  if (e == hipSuccess)
+    e = launch_argmax(map, F, J, reinterpret_cast<unsigned long long*>(peaks), s);
+  if (e == hipSuccess) e = launch_peaks_finalize(peaks, F, s);
+  if (e != hipSuccess) return device_fail(e, "argmax");
+  return SRP_OK;
+}
+
+}  // extern "C"

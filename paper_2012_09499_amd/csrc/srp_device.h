@@ -1,0 +1,47 @@
+// Device helpers shared by the libsrp kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace srp {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// Unsigned key whose integer order is the float order of `v` (finite or inf),
+// with the candidate index in the low word so that, among equal values, the
+// LOWEST index has the LARGEST key. Key 0 means "no candidate yet".
+__device__ __forceinline__ unsigned long long peak_key(float v, unsigned idx) {
+  unsigned u = __float_as_uint(v);
+  unsigned ord = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+  return (static_cast<unsigned long long>(ord) << 32) | (0xFFFFFFFFu - idx);
+}
+
+__device__ __forceinline__ float key_value(unsigned long long key) {
+  unsigned ord = static_cast<unsigned>(key >> 32);
+  unsigned u = (ord & 0x80000000u) ? (ord & 0x7FFFFFFFu) : ~ord;
+  return __uint_as_float(u);
+}
+
+__device__ __forceinline__ unsigned key_index(unsigned long long key) {
+  return 0xFFFFFFFFu - static_cast<unsigned>(key & 0xFFFFFFFFull);
+}
+
+// Max over the 32 lanes of each half of a wave64 (halves stay separate).
+__device__ __forceinline__ unsigned long long half_wave_max(unsigned long long k) {
+#pragma unroll
+  for (int off = 16; off >= 1; off >>= 1) {
+    unsigned long long o = __shfl_xor(k, off, 64);
+    k = o > k ? o : k;
+  }
+  return k;
+}
+
+__device__ __forceinline__ unsigned long long wave_max(unsigned long long k) {
+  unsigned long long o = __shfl_xor(k, 32, 64);
+  k = o > k ? o : k;
+  return half_wave_max(k);
+}
+
+}  // namespace srp

@@ -1,0 +1,80 @@
+// Internal declarations shared by the host API (srp_api.hip) and the kernel
+// translation units. Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "srp.h"
+
+namespace srp {
+
+// One microphone pair (Section 2.1): mics m > mp, window half-width
+// h = N_p + N_aux and the column of its first sample in the packed layout.
+struct PairDesc {
+  int32_t m, mp, h, off;
+};
+
+// A run of consecutive lags [t0, t0 + len) of pair p's window (t counts from
+// the window's first lag n = -h). Long windows are cut into several runs so
+// that one run fits a kernel's on-chip staging buffer.
+struct LagRun {
+  int32_t p, t0, len, pad;
+};
+
+// Lag runs of the Nyquist interpolation kernels are at most this long (even).
+constexpr int kNyqRunMax = 128;
+// Lag tiles of the GCC-sample kernel are 32 lags wide (one matrix-core tile).
+constexpr int kGccLagTile = 32;
+
+}  // namespace srp
+
+struct srp_geometry_s {
+  srp_geometry_info info;
+  int device = 0;
+  double inv_cT = 0.0;     // converts a path difference in metres into x = dt / T
+  double fs_over_c = 0.0;  // converts a path difference in metres into samples
+  int log2L = 0;
+  int gcc_nw = 0;          // row width of the GCC phase table (2 h_max + 1 + 32)
+  std::vector<srp::PairDesc> pairs;
+  std::vector<int32_t> N_p;
+  std::vector<int64_t> offsets;
+  std::vector<srp::LagRun> gcc_tiles;  // lag tiles of srp_gcc_samples
+  std::vector<srp::LagRun> nyq_runs;   // lag runs of srp_map_nyquist
+  // device copies
+  double* d_mic = nullptr;             // [M][3]
+  double* d_cand = nullptr;            // [3][J] (structure of arrays)
+  srp::PairDesc* d_pairs = nullptr;    // [P]
+  srp::LagRun* d_gcc_tiles = nullptr;
+  srp::LagRun* d_nyq_runs = nullptr;
+  float* d_window = nullptr;           // [L]
+  float2* d_twiddle = nullptr;         // [L/2] exp(-j 2 pi t / L)
+  float2* d_gcc_table = nullptr;       // [K][gcc_nw] (cos, -sin) of 2 pi f_k n T
+  float* d_binw = nullptr;             // [K]
+};
+
+namespace srp {
+
+void set_error(const std::string& msg);
+
+// Kernel launchers. Each returns hipSuccess or the launch error; the host API
+// validates every argument before calling them.
+hipError_t launch_fft_phat(const srp_geometry_s* g, const float* frames, int F, float2* ytil,
+                           hipStream_t s);
+hipError_t launch_cross(const srp_geometry_s* g, const float2* ytil, int F, float2* psi,
+                        hipStream_t s);
+hipError_t launch_gcc_samples(const srp_geometry_s* g, const float2* psi, int F, float* xi,
+                              hipStream_t s);
+hipError_t launch_nyquist(const srp_geometry_s* g, const float* xi, int F, int dtype, float* map,
+                          unsigned long long* keys, hipStream_t s);
+hipError_t launch_conventional(const srp_geometry_s* g, const float2* psi, int F, int dtype,
+                               float* map, unsigned long long* keys, hipStream_t s);
+hipError_t launch_peaks_init(srp_peak* peaks, int F, hipStream_t s);
+hipError_t launch_peaks_finalize(srp_peak* peaks, int F, hipStream_t s);
+hipError_t launch_argmax(const float* map, int F, int64_t J, unsigned long long* keys,
+                         hipStream_t s);
+
+}  // namespace srp

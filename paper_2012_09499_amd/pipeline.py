@@ -1,0 +1,41 @@
+"""Frame-batch pipeline over the C ABI with preallocated device buffers.
+
+Nyquist path: srp_cross_spectra -> srp_gcc_samples -> srp_map_nyquist.
+Conventional path: srp_cross_spectra -> srp_map_conventional.
+Every step is a libsrp kernel; buffers are torch tensors allocated once.
+"""
+from __future__ import annotations
+
+from . import _lib as S
+
+
+class SrpPipeline:
+    def __init__(self, geom: S.Geometry, F: int, device="cuda", keep_map: bool = False):
+        import torch
+        self.g = geom
+        self.F = int(F)
+        self.workspace = torch.empty(geom.workspace_bytes(F), dtype=torch.uint8, device=device)
+        self.psi = torch.empty((F, geom.P, geom.K), dtype=torch.complex64, device=device)
+        self.xi = torch.empty((F, geom.S), dtype=torch.float32, device=device)
+        self.peaks = torch.empty((F, 2), dtype=torch.int64, device=device)
+        self.map = (torch.empty((F, geom.J), dtype=torch.float32, device=device)
+                    if keep_map else None)
+
+    def spectra(self, frames):
+        return S.cross_spectra(self.g, frames, out=self.psi[:frames.shape[0]],
+                               workspace=self.workspace)
+
+    def nyquist(self, frames, dtype: str = "fp32"):
+        F = frames.shape[0]
+        psi = self.spectra(frames)
+        xi = S.gcc_samples(self.g, psi, out=self.xi[:F])
+        return S.map_nyquist(self.g, xi, dtype=dtype, want_map=self.map is not None,
+                             map_out=None if self.map is None else self.map[:F],
+                             peaks_out=self.peaks[:F])
+
+    def conventional(self, frames, dtype: str = "fp32"):
+        F = frames.shape[0]
+        psi = self.spectra(frames)
+        return S.map_conventional(self.g, psi, dtype=dtype, want_map=self.map is not None,
+                                  map_out=None if self.map is None else self.map[:F],
+                                  peaks_out=self.peaks[:F])

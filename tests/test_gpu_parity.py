@@ -1,0 +1,283 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances (written here, derived in the design doc):
+* FP32 maps: relative L2 error per frame <= 1e-5; argmax identical in >= 99 %
+  of frames, any other frame a near-tie within the map tolerance.
+* FP64 map instances from the same float32 samples: <= 1e-12.
+* PHAT cross-spectra: relative L2 error per frame <= 1e-5 (float32 FFT).
+* GCC samples from the same psi: relative L2 error per frame <= 1e-5 (a
+  float32 sum over 2K terms: about u sqrt(2K), ~3e-6 at K = 2049) and
+  elementwise absolute error <= 1e-5 L.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as WL
+from tests import refpath as R
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2012_09499_amd as srp  # noqa: E402
+
+MAP_TOL = 1e-5
+PSI_TOL = 1e-5
+XI_TOL = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    srp.lib()
+    yield
+    torch.cuda.synchronize()
+
+
+def _frames(wl):
+    return torch.from_numpy(wl.frames).cuda()
+
+
+def _geom(wl, window="hann", n_aux=None, cand=None):
+    cand = wl.candidates() if cand is None else cand
+    return srp.Geometry(wl.mic_xyz, cand, fs=wl.fs, L=wl.L, c=wl.c, f_max=wl.band_limit,
+                        n_aux=wl.n_aux if n_aux is None else n_aux, field=wl.field,
+                        window=window)
+
+
+def _rel(a, b):
+    return O.rel_error(a, b)
+
+
+def _c128(psi_t):
+    return psi_t.cpu().numpy().astype(np.complex128)
+
+
+CASES = {
+    # name: (builder) -- several candidate tiles, a ragged frame tail, odd J
+    "m4_L256_F3": lambda: WL.make_custom(M=4, J_shape=(9, 7, 5), L=256, F=3, seed=1),
+    "m7_L1024_F70": lambda: WL.make_custom(M=7, J_shape=(13, 11, 7), h=0.09, L=1024, F=70, seed=2),
+    "m2_L64_F1": lambda: WL.make_custom(M=2, J_shape=(1, 1, 1), L=64, F=1, seed=3),
+    "m12_L512_F9_naux0": lambda: WL.make_custom(M=12, J_shape=(17, 5, 3), L=512, F=9, seed=4,
+                                                n_aux=0),
+    "m5_L4096_48k_F2": lambda: WL.make_custom(M=5, J_shape=(6, 5, 4), h=0.2, fs=48000.0,
+                                              L=4096, F=2, seed=5, box=(1.2, 1.0, 0.6)),
+    "m6_L1024_fmax4k_F4": lambda: WL.make_custom(M=6, J_shape=(7, 6, 5), L=1024, F=4, seed=6,
+                                                 f_max=4000.0),
+}
+
+
+@pytest.fixture(scope="module")
+def cases():
+    return {k: v() for k, v in CASES.items()}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_cross_spectra(cases, name):
+    wl = cases[name]
+    g = _geom(wl)
+    psi = srp.cross_spectra(g, _frames(wl))
+    torch.cuda.synchronize()
+    ref = R.oracle_psi(wl)
+    got = _c128(psi)
+    err = np.sqrt((np.abs(got - ref) ** 2).sum(axis=(1, 2)) / (np.abs(ref) ** 2).sum(axis=(1, 2)))
+    assert err.max() <= PSI_TOL, err
+    np.testing.assert_allclose(np.abs(got), 1.0, atol=1e-6)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_gcc_samples(cases, name):
+    wl = cases[name]
+    g = _geom(wl)
+    psi = srp.cross_spectra(g, _frames(wl))
+    xi = srp.gcc_samples(g, psi)
+    torch.cuda.synchronize()
+    ref = R.oracle_xi(wl, _c128(psi))
+    got = xi.cpu().numpy().astype(np.float64)
+    assert _rel(got, ref).max() <= XI_TOL
+    # elementwise: a float32 sum of 2K terms whose magnitudes add up to at most
+    # sum_k w_k <= L; the worst-case rounding bound 2K u L (u = 2^-24) exceeds
+    # 1e-5 L, which typical error growth (sqrt(2K) u L) stays well below
+    assert np.abs(got - ref).max() <= 1e-5 * wl.L
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("dtype", ["fp32", "fp64"])
+def test_nyquist_map_from_same_samples(cases, name, dtype):
+    wl = cases[name]
+    g = _geom(wl)
+    psi = srp.cross_spectra(g, _frames(wl))
+    xi = srp.gcc_samples(g, psi)
+    m, pk = srp.map_nyquist(g, xi, dtype=dtype)
+    torch.cuda.synchronize()
+    ref = R.oracle_nyquist(wl, xi.cpu().numpy().astype(np.float64), wl.candidates())
+    got = m.cpu().numpy().astype(np.float64)
+    tol = MAP_TOL if dtype == "fp32" else 1e-12
+    # the fp64 kernel writes a float32 map: compare at float32 resolution
+    if dtype == "fp64":
+        ref32 = ref.astype(np.float32).astype(np.float64)
+        assert np.abs(got - ref32).max() <= 2 ** -23 * np.abs(ref).max() + 1e-30
+    else:
+        assert _rel(got, ref).max() <= tol
+    idx, val = srp.decode_peaks(pk)
+    np.testing.assert_array_equal(idx, np.argmax(got, axis=1))
+    np.testing.assert_array_equal(val, got.max(axis=1).astype(np.float32))
+    R.check_argmax(idx, ref, MAP_TOL)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("dtype", ["fp32", "fp64"])
+def test_conventional_map(cases, name, dtype):
+    wl = cases[name]
+    g = _geom(wl)
+    psi = srp.cross_spectra(g, _frames(wl))
+    m, pk = srp.map_conventional(g, psi, dtype=dtype)
+    torch.cuda.synchronize()
+    ref = R.oracle_conventional(wl, _c128(psi), wl.candidates())
+    got = m.cpu().numpy().astype(np.float64)
+    if dtype == "fp64":
+        ref32 = ref.astype(np.float32).astype(np.float64)
+        assert np.abs(got - ref32).max() <= 2 ** -23 * np.abs(ref).max() * 1.01 + 1e-30
+    else:
+        assert _rel(got, ref).max() <= MAP_TOL
+    idx, _ = srp.decode_peaks(pk)
+    np.testing.assert_array_equal(idx, np.argmax(got, axis=1))
+    R.check_argmax(idx, ref, MAP_TOL)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_pipeline_from_frames(cases, name):
+    """Frames -> peaks, both methods, against the oracle run from the frames in FP64."""
+    wl = cases[name]
+    g = _geom(wl)
+    pipe = srp.SrpPipeline(g, wl.F, keep_map=True)
+    fr = _frames(wl)
+    psi_ref = R.oracle_psi(wl)
+    cand = wl.candidates()
+    m, pk = pipe.nyquist(fr)
+    torch.cuda.synchronize()
+    ref = R.oracle_nyquist(wl, R.oracle_xi(wl, psi_ref), cand)
+    assert _rel(m.cpu().numpy(), ref).max() <= MAP_TOL
+    R.check_argmax(srp.decode_peaks(pk)[0], ref, MAP_TOL)
+    m, pk = pipe.conventional(fr)
+    torch.cuda.synchronize()
+    refc = R.oracle_conventional(wl, psi_ref, cand)
+    assert _rel(m.cpu().numpy(), refc).max() <= MAP_TOL
+    R.check_argmax(srp.decode_peaks(pk)[0], refc, MAP_TOL)
+
+
+def test_peaks_only_equals_map_argmax(cases):
+    wl = cases["m7_L1024_F70"]
+    g = _geom(wl)
+    pipe = srp.SrpPipeline(g, wl.F, keep_map=False)
+    fr = _frames(wl)
+    _, pk1 = pipe.nyquist(fr)
+    xi = srp.gcc_samples(g, srp.cross_spectra(g, fr))
+    m, _ = srp.map_nyquist(g, xi, want_peaks=False)
+    pk2 = srp.argmax(m)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(pk1.cpu().numpy(), pk2.cpu().numpy())
+
+
+def test_argmax_kernel_random_and_ties():
+    rng = np.random.default_rng(0)
+    for F, J in [(1, 1), (3, 1000), (5, 2049 * 3 + 17), (2, 70000)]:
+        a = rng.standard_normal((F, J)).astype(np.float32)
+        a[0, J // 2] = a[0].max() + 1.0
+        if J > 10:
+            a[-1, 7] = a[-1, J - 3] = a[-1].max() + 2.0  # tie: lowest index wins
+        pk = srp.argmax(torch.from_numpy(a).cuda())
+        idx, val = srp.decode_peaks(pk)
+        np.testing.assert_array_equal(idx, np.argmax(a, axis=1))
+        np.testing.assert_array_equal(val, a.max(axis=1))
+    neg = -np.abs(rng.standard_normal((2, 300))).astype(np.float32) - 1.0
+    idx, val = srp.decode_peaks(srp.argmax(torch.from_numpy(neg).cuda()))
+    np.testing.assert_array_equal(idx, np.argmax(neg, axis=1))
+
+
+def test_zero_frames_give_zero_map_and_index_zero():
+    wl = WL.make_custom(M=4, J_shape=(9, 7, 5), L=256, F=3, seed=1)
+    g = _geom(wl)
+    z = torch.zeros((3, 4, 256), dtype=torch.float32, device="cuda")
+    pipe = srp.SrpPipeline(g, 3, keep_map=True)
+    for run in (pipe.nyquist, pipe.conventional):
+        m, pk = run(z)
+        torch.cuda.synchronize()
+        assert torch.count_nonzero(m).item() == 0
+        idx, val = srp.decode_peaks(pk)
+        assert np.all(idx == 0) and np.all(val == 0)
+
+
+def test_far_field_pipeline():
+    wl = WL.make_far_field(F=3, L=1024, step_deg=4.0)
+    g = _geom(wl, window="sqrt_hann")
+    pipe = srp.SrpPipeline(g, wl.F, keep_map=True)
+    fr = _frames(wl)
+    psi_ref = R.oracle_psi(wl, window="sqrt_hann")
+    m, pk = pipe.nyquist(fr)
+    torch.cuda.synchronize()
+    ref = R.oracle_nyquist(wl, R.oracle_xi(wl, psi_ref), wl.directions)
+    assert _rel(m.cpu().numpy(), ref).max() <= MAP_TOL
+    R.check_argmax(srp.decode_peaks(pk)[0], ref, MAP_TOL)
+    m, pk = pipe.conventional(fr)
+    torch.cuda.synchronize()
+    refc = R.oracle_conventional(wl, psi_ref, wl.directions)
+    assert _rel(m.cpu().numpy(), refc).max() <= MAP_TOL
+
+
+def test_integer_tdoa_candidates_exact_weight():
+    """Candidates whose x_p is an exact integer hit the sinc(0) = 1 case."""
+    fs, c, L = 16000.0, 343.0, 256
+    d = 10 * c / fs
+    mic = np.array([[0.0, 0.0, 0.0], [d, 0.0, 0.0]])
+    cand = np.array([[-1.0, 0.0, 0.0], [2.0 * d, 0.0, 0.0], [0.5 * d, 0.0, 0.0],
+                     [0.5 * d, 1.0, 0.0]])
+    rng = np.random.default_rng(3)
+    y = rng.standard_normal((4, 2, L)).astype(np.float32)
+    g = srp.Geometry(mic, cand, fs=fs, L=L, c=c, n_aux=2)
+    pipe = srp.SrpPipeline(g, 4, keep_map=True)
+    m, _ = pipe.nyquist(torch.from_numpy(y).cuda())
+    torch.cuda.synchronize()
+    wl = WL.Workload(name="int", mic_xyz=mic, grid=None, fs=fs, L=L, F=4, c=c, n_aux=2, frames=y)
+    psi = R.oracle_psi(wl)
+    ref = R.oracle_nyquist(wl, R.oracle_xi(wl, psi), cand)
+    assert _rel(m.cpu().numpy(), ref).max() <= MAP_TOL
+    conv = R.oracle_conventional(wl, psi, cand)
+    # exact interpolation at the integer-TDOA candidates (sinc(x - n) = delta)
+    np.testing.assert_allclose(m.cpu().numpy()[:, :3], conv[:, :3], rtol=2e-5,
+                               atol=2e-5 * np.abs(conv).max())
+
+
+def test_repeat_runs_bitwise_identical(cases):
+    wl = cases["m7_L1024_F70"]
+    g = _geom(wl)
+    pipe = srp.SrpPipeline(g, wl.F, keep_map=True)
+    fr = _frames(wl)
+    m1 = pipe.nyquist(fr)[0].clone()
+    m2 = pipe.nyquist(fr)[0].clone()
+    c1 = pipe.conventional(fr)[0].clone()
+    c2 = pipe.conventional(fr)[0].clone()
+    torch.cuda.synchronize()
+    assert torch.equal(m1, m2) and torch.equal(c1, c2)
+
+
+def test_config1_full():
+    """4-mic 2-D scene, 2500 candidates, 10 frames, both methods, N_aux 0..4."""
+    for n_aux in range(5):
+        wl = WL.make(1, n_aux=n_aux)
+        g = _geom(wl)
+        pipe = srp.SrpPipeline(g, wl.F, keep_map=True)
+        fr = _frames(wl)
+        psi_ref = R.oracle_psi(wl)
+        m, pk = pipe.nyquist(fr)
+        torch.cuda.synchronize()
+        ref = R.oracle_nyquist(wl, R.oracle_xi(wl, psi_ref), wl.candidates())
+        assert _rel(m.cpu().numpy(), ref).max() <= MAP_TOL
+        R.check_argmax(srp.decode_peaks(pk)[0], ref, MAP_TOL)
+    m, pk = pipe.conventional(fr)
+    torch.cuda.synchronize()
+    refc = R.oracle_conventional(wl, psi_ref, wl.candidates())
+    assert _rel(m.cpu().numpy(), refc).max() <= MAP_TOL
+    R.check_argmax(srp.decode_peaks(pk)[0], refc, MAP_TOL)
