@@ -1,0 +1,209 @@
+"""Benchmark: SRP candidate-pair evaluations per second on one MI355X.
+
+Workload (default): the room-scale configuration -- 16 microphones uniformly
+random in a 1 x 1 x 0.5 m box (120 pairs), fs = 16 kHz, 1024-sample Hann
+frames (513 bins), a 6 x 4 x 3 m room gridded at 5 cm (576,000 candidates),
+500 frames of seeded free-field white-noise sources with 10 dB sensor noise,
+N_aux = 2. Inputs are synthetic (workloads.make(2)) and already resident in
+device memory when the timed region starts.
+
+One step = one pass of the Nyquist hot path over the 500-frame batch:
+srp_cross_spectra (windowed FFT + PHAT cross-spectra), srp_gcc_samples (GCC
+samples at the critical lags), srp_map_nyquist (TDOA + sinc interpolation +
+pair sum + per-frame argmax). `value` = F * J * P / step time. The
+conventional map (srp_cross_spectra + srp_map_conventional) is timed beside
+it on the same frames and reported under "conventional".
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3   # MI355X dense FP32 (matrix cores), published
+PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_nyquist_f32_cfg2.json")
+
+
+def kernel_source_hash() -> str:
+    p = os.path.join(ROOT, "paper_2012_09499_amd", "csrc", "k_nyquist.hip")
+    with open(p, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic(bytes_per_launch_alg: float):
+    """HBM bytes per launch from committed rocprofv3 PMC runs, if still current."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        t = json.load(f)
+    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(wl, n_cand: int, seed: int = 0):
+    """The FP64 oracle on a bounded sample: all frames, a seeded candidate subset."""
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()
+                            if i.get("user_api") == "blas"] or [1])
+    except Exception:
+        blas_threads = 1
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(wl.J, size=min(n_cand, wl.J), replace=False))
+    cand = wl.candidates_at(idx)
+    t0 = time.perf_counter()
+    K = O.n_bins(wl.L, wl.fs)
+    w = O.bin_weights(wl.L, K)
+    win = O.pair_windows(wl.mic_xyz, wl.c, wl.fs / 2, wl.n_aux)
+    psi = O.phat_cross_spectra(O.spectra(wl.frames, O.window(wl.L), K))
+    xi = O.gcc_samples(psi, wl.fs, wl.L, w, win)
+    dt = O.tdoa(wl.mic_xyz, cand, wl.c)
+    ref = O.srp_nyquist(xi, dt, win)
+    O.peaks(ref)
+    sec = time.perf_counter() - t0
+    rate = wl.F * idx.size * wl.P / sec
+    info = {"value": rate, "unit": "cand-pair evals/s", "cores": int(blas_threads),
+            "kind": "oracle", "seconds": sec, "host_cpu_count": os.cpu_count(),
+            "sample": (f"all {wl.F} frames, {idx.size} of {wl.J} candidates (seeded random); "
+                       f"spectra + PHAT + GCC samples + Nyquist map + argmax in float64 NumPy; "
+                       f"elementwise steps single-threaded, matrix products on "
+                       f"{blas_threads} BLAS threads")}
+    return info, idx, ref
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--conv-steps", type=int, default=3)
+    ap.add_argument("--no-conventional", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-candidates", type=int, default=40000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): the SRP path "
+              "shards over candidates with no exchange except a per-frame argmax reduction, "
+              "and this build has no multi-GPU launcher.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2012_09499_amd as srp
+    import workloads as WL
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    t_gen = time.perf_counter()
+    wl = WL.make(args.config)
+    print(f"[bench] workload {wl.name}: M={wl.M} P={wl.P} J={wl.J} F={wl.F} L={wl.L} "
+          f"(generated in {time.perf_counter() - t_gen:.1f}s)", file=sys.stderr, flush=True)
+    g = srp.Geometry(wl.mic_xyz, wl.candidates(), fs=wl.fs, L=wl.L, c=wl.c, n_aux=wl.n_aux)
+    pipe = srp.SrpPipeline(g, wl.F, device=dev, keep_map=False)
+    frames = torch.from_numpy(wl.frames).to(dev)
+    stream = torch.cuda.current_stream()
+
+    def nyquist_step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        psi = srp.cross_spectra(g, frames, out=pipe.psi, workspace=pipe.workspace)
+        if ev is not None:
+            ev[1].record(stream)
+        xi = srp.gcc_samples(g, psi, out=pipe.xi)
+        if ev is not None:
+            ev[2].record(stream)
+        srp.map_nyquist(g, xi, want_map=False, peaks_out=pipe.peaks)
+        if ev is not None:
+            ev[3].record(stream)
+
+    for _ in range(args.warmup):
+        nyquist_step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        nyquist_step(evs[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    t_spec = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    t_gcc = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    t_map = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
+    evals = float(wl.F) * wl.J * wl.P
+    value = evals / (ms_step * 1e-3)
+    print(f"[bench] nyquist fp32: {ms_step:.3f} ms/step (spectra {t_spec:.3f}, gcc {t_gcc:.3f}, "
+          f"map {t_map:.3f} ms)", file=sys.stderr, flush=True)
+
+    flops_map = 2.0 * g.S * wl.J * wl.F          # 2 N P J per frame (Eq. SRPapproxcompR)
+    flops_gcc = 4.0 * g.S * g.K * wl.F           # N P K complex MACs, real part (Eq. SRPapproxcompC)
+    achieved = flops_map / (t_map * 1e-3) / 1e12
+    traffic = load_traffic(flops_map)
+    roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
+                "kernel": "nyquist_f32_kernel (srp_map_nyquist, FP32 MFMA 32x32x2)",
+                "algorithmic_flops_per_launch": flops_map,
+                "avg_launch_ms": t_map}
+
+    out = {"metric": "SRP candidate-pair evals/s (Nyquist, FP32)", "value": value,
+           "unit": "cand-pair evals/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic (seeded free-field white-noise sources, 10 dB sensor noise)",
+           "config": {"workload": wl.name, "M": wl.M, "P": wl.P, "J": wl.J, "F": wl.F,
+                      "L": wl.L, "K": g.K, "fs": wl.fs, "n_aux": wl.n_aux, "S": g.S,
+                      "N_avg_samples_per_pair": g.S / wl.P},
+           "roofline": roofline,
+           "kernels_ms": {"cross_spectra": t_spec, "gcc_samples": t_gcc, "map_nyquist": t_map},
+           "gcc_samples_tflops": flops_gcc / (t_gcc * 1e-3) / 1e12}
+
+    if not args.no_conventional:
+        def conv_step():
+            psi = srp.cross_spectra(g, frames, out=pipe.psi, workspace=pipe.workspace)
+            srp.map_conventional(g, psi, want_map=False, peaks_out=pipe.peaks)
+        conv_step()
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        for _ in range(args.conv_steps):
+            conv_step()
+        torch.cuda.synchronize()
+        ms_conv = (time.perf_counter() - c0) * 1e3 / args.conv_steps
+        flops_conv = 4.0 * g.K * wl.P * wl.J * wl.F   # J P K complex MACs, real part (Eq. SRPomp)
+        out["conventional"] = {"value": evals / (ms_conv * 1e-3), "unit": "cand-pair evals/s",
+                               "ms_per_step": ms_conv, "steps": args.conv_steps,
+                               "algorithmic_tflops": flops_conv / (ms_conv * 1e-3) / 1e12,
+                               "nyquist_speedup": ms_conv / ms_step}
+        print(f"[bench] conventional fp32: {ms_conv:.1f} ms/step", file=sys.stderr, flush=True)
+
+    if not args.no_cpu_baseline:
+        cb, idx, ref = cpu_baseline(wl, args.cpu_candidates)
+        out["cpu_baseline"] = cb
+        # parity of the timed configuration on the sampled candidates (not timed)
+        keep = srp.SrpPipeline(g, wl.F, device=dev, keep_map=True)
+        m, pk = keep.nyquist(frames)
+        sub = m[:, torch.from_numpy(idx).to(dev)].cpu().numpy().astype(np.float64)
+        err = np.sqrt(((sub - ref) ** 2).sum(1) / (ref ** 2).sum(1))
+        out["parity_sampled"] = {"candidates": int(idx.size), "max_rel_err": float(err.max()),
+                                 "median_rel_err": float(np.median(err))}
+        print(f"[bench] cpu baseline {cb['value']:.3e} evals/s on {cb['cores']} BLAS threads "
+              f"({cb['seconds']:.1f}s); sampled map rel err max {err.max():.2e}",
+              file=sys.stderr, flush=True)
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
