@@ -16,13 +16,15 @@
 namespace srp {
 namespace {
 
-constexpr int kKC = 32;          // bins per LDS chunk (16 steps)
-constexpr int kCStride = kKC + 1;
+constexpr int kKC = 32;          // bins per staged run (16 steps)
+constexpr int kCStride = 2 * kKC + 1;  // LDS row stride (odd): interleaved re, im
 
 struct ConvArgs {
   const double* cand;
   const double* mic;
   const PairDesc* pairs;
+  const LagRun* runs;  // bin runs (p, k0, len), an even number of them
+  int n_runs;
   int P;
   const float2* psi;   // [F][P][K]
   const float* binw;   // [K]
@@ -36,10 +38,10 @@ struct ConvArgs {
   unsigned long long* keys;
 };
 
-__device__ __forceinline__ double pair_xs(const ConvArgs& a, const PairDesc& pd, double qx,
-                                          double qy, double qz) {
-  const double* pm = a.mic + 3 * pd.m;
-  const double* pn = a.mic + 3 * pd.mp;
+__device__ __forceinline__ double pair_xs(const ConvArgs& a, const double* __restrict__ mic,
+                                          const PairDesc& pd, double qx, double qy, double qz) {
+  const double* pm = mic + 3 * pd.m;
+  const double* pn = mic + 3 * pd.mp;
   if (a.far_field) {
     return ((pm[0] - pn[0]) * qx + (pm[1] - pn[1]) * qy + (pm[2] - pn[2]) * qz) * a.fs_over_c;
   }
@@ -54,33 +56,152 @@ __device__ __forceinline__ void phasor_turns(double v, float* c, float* s) {
   sincospif(2.0f * t, s, c);
 }
 
+// Asynchronous copy of one bin run of pair p (interleaved re, im; 2 len
+// floats per frame row) into the LDS tile [frame][2 * kKC]; wave w copies rows
+// w, w + 4, ... below nrows. Lanes past the run copy its last float.
+__device__ __forceinline__ void stage_bins(const ConvArgs& a, const LagRun& run, float* tile,
+                                           int f0, int nrows, int wave, int lane) {
+  typedef __attribute__((address_space(3))) void* lds_ptr;
+  if (run.len <= 0) return;
+  const int n = 2 * run.len;
+  const int t = lane < n ? lane : n - 1;
+  const float* src = reinterpret_cast<const float*>(a.psi) +
+                     2 * (((size_t)(f0 + wave) * a.P + run.p) * a.K + run.t0) + t;
+  const size_t step = 8 * (size_t)a.P * a.K;  // 4 frames of 2 K floats per pair
+  float* dst = tile + wave * kCStride;
+  for (int f = wave; f < nrows; f += 4) {
+    __builtin_amdgcn_global_load_lds(src, (lds_ptr)dst, 4, 0, 0);
+    src += step;
+    dst += 4 * kCStride;
+  }
+}
+
+template <int CT>
+struct ConvLane {
+  double qx[CT], qy[CT], qz[CT];
+  double xs[CT];     // dt fs (samples) for the current pair
+  float rc[CT], rs[CT];  // rotation through two bins
+  int cur_p;
+};
+
+// Contracts one staged bin run into acc: A = (re, im) of psi from LDS,
+// B = (w'_k cos theta, -w'_k sin theta) with w'_k = w_k / 2 (the factor 2 of
+// the interior bins is applied in the epilogue).
 template <int CT, int FT>
-__global__ __launch_bounds__(256) void conventional_f32_kernel(ConvArgs a) {
+__device__ __forceinline__ void conv_run(const ConvArgs& a, const double* __restrict__ mic,
+                                         const PairDesc* __restrict__ pairs,
+                                         const LagRun& run, ConvLane<CT>& st,
+                                         const float* tile, int cl, int g,
+                                         floatx16 (&acc)[CT][FT]) {
+  if (run.len <= 0) return;
+  if (run.p != st.cur_p) {
+    st.cur_p = run.p;
+    const PairDesc pd = pairs[run.p];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      st.xs[ct] = pair_xs(a, mic, pd, st.qx[ct], st.qy[ct], st.qz[ct]);
+      phasor_turns(2.0 * st.xs[ct] / a.L, &st.rc[ct], &st.rs[ct]);
+    }
+  }
+  float cs[CT], sn_[CT];
+  int k = run.t0 + g;  // this lane's bin at step 0
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct)
+    phasor_turns(static_cast<double>(k) * st.xs[ct] / a.L, &cs[ct], &sn_[ct]);
+  const float* rrow = tile + cl * kCStride + 2 * g;
+  const int steps = (run.len + 1) >> 1;
+  const int kend = run.t0 + run.len < a.K ? run.t0 + run.len : a.K;
+  // software pipeline, two steps per iteration with ping-pong operand sets:
+  // the LDS operands of the next step are read while the matrix cores work on
+  // the current one
+  float ar0[FT], ai0[FT], ar1[FT], ai1[FT];
+  auto fetch = [&](int s, float (&ar)[FT], float (&ai)[FT]) {
+    const int sc = s < steps ? s : steps - 1;
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft) {
+      ar[ft] = rrow[ft * 32 * kCStride + 4 * sc];
+      ai[ft] = rrow[ft * 32 * kCStride + 4 * sc + 1];
+    }
+  };
+  auto contract = [&](const float (&ar)[FT], const float (&ai)[FT]) {
+    const float wk = k >= kend ? 0.0f : (k == 0 || 2 * k == a.L) ? 0.5f : 1.0f;
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      const float bc = wk * cs[ct];
+      const float bs = -wk * sn_[ct];
+#pragma unroll
+      for (int ft = 0; ft < FT; ++ft) {
+        acc[ct][ft] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[ft], bc, acc[ct][ft], 0, 0, 0);
+        acc[ct][ft] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[ft], bs, acc[ct][ft], 0, 0, 0);
+      }
+      const float c2 = cs[ct] * st.rc[ct] - sn_[ct] * st.rs[ct];
+      const float s2 = cs[ct] * st.rs[ct] + sn_[ct] * st.rc[ct];
+      cs[ct] = c2;
+      sn_[ct] = s2;
+    }
+    k += 2;
+  };
+  auto order = [&]() {
+    // one matrix-core instruction (operands read a half-iteration earlier),
+    // then the next step's LDS reads, then the rest with VALU work between
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x100, 2 * FT, 0);
+#pragma unroll
+    for (int i = 1; i < 2 * CT * FT; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x002, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    }
+  };
+  fetch(0, ar0, ai0);
+  int s = 0;
+  for (; s + 1 < steps; s += 2) {
+    fetch(s + 1, ar1, ai1);
+    contract(ar0, ai0);
+    order();
+    fetch(s + 2, ar0, ai0);
+    contract(ar1, ai1);
+    order();
+  }
+  if (s < steps) contract(ar0, ai0);
+}
+
+// mic, pairs and runs arrive as __restrict__ const kernel parameters so that
+// their uniform reads are scalar loads (they then never wait on the
+// asynchronous LDS copies in flight).
+template <int CT, int FT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void conventional_f32_kernel(ConvArgs a, const double* __restrict__ mic,
+                             const PairDesc* __restrict__ pairs,
+                             const LagRun* __restrict__ runs) {
   constexpr int FB = 32 * FT;
   constexpr int JW = 32 * CT;
   constexpr int JB = 4 * JW;
-  __shared__ float re_s[FB * kCStride];
-  __shared__ float im_s[FB * kCStride];
+  __shared__ float ps0[FB * kCStride];
+  __shared__ float ps1[FB * kCStride];
   __shared__ unsigned long long kbest[FB];
 
   const int tid = threadIdx.x;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
   const int cl = lane & 31;
   const int g = lane >> 5;
   const int64_t jb = (int64_t)blockIdx.x * JB + wave * JW;
   const int f0 = blockIdx.y * FB;
-  const double invL = 1.0 / a.L;
+  const int nrows = a.F - f0 < FB ? a.F - f0 : FB;
 
-  double qx[CT], qy[CT], qz[CT];
+  ConvLane<CT> st;
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) {
     int64_t ci = jb + ct * 32 + cl;
     ci = ci < a.J ? ci : a.J - 1;
-    qx[ct] = a.cand[ci];
-    qy[ct] = a.cand[a.J + ci];
-    qz[ct] = a.cand[2 * a.J + ci];
+    st.qx[ct] = a.cand[ci];
+    st.qy[ct] = a.cand[a.J + ci];
+    st.qz[ct] = a.cand[2 * a.J + ci];
+    st.xs[ct] = 0.0;
+    st.rc[ct] = 1.0f;
+    st.rs[ct] = 0.0f;
   }
+  st.cur_p = -1;
   for (int i = tid; i < FB; i += 256) kbest[i] = 0ull;
 
   floatx16 acc[CT][FT];
@@ -91,64 +212,20 @@ __global__ __launch_bounds__(256) void conventional_f32_kernel(ConvArgs a) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[ct][ft][r] = 0.0f;
 
-  for (int p = 0; p < a.P; ++p) {
-    const PairDesc pd = a.pairs[p];
-    double xs[CT];
-    float rc[CT], rs[CT];
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct) {
-      xs[ct] = pair_xs(a, pd, qx[ct], qy[ct], qz[ct]);
-      phasor_turns(2.0 * xs[ct] * invL, &rc[ct], &rs[ct]);  // rotation by two bins
-    }
-    const float2* prow = a.psi + (size_t)p * a.K;
-    for (int k0 = 0; k0 < a.K; k0 += kKC) {
-      __syncthreads();
-      // stage w_k Re psi and -w_k Im psi as [frame][bin]
-      for (int row = 2 * wave + g; row < FB; row += 8) {
-        const int fg = f0 + row;
-        const int k = k0 + cl;
-        float vr = 0.0f, vi = 0.0f;
-        if (fg < a.F && k < a.K) {
-          const float2 v = prow[(size_t)fg * a.P * a.K + k];
-          const float w = a.binw[k];
-          vr = w * v.x;
-          vi = -w * v.y;
-        }
-        re_s[row * kCStride + cl] = vr;
-        im_s[row * kCStride + cl] = vi;
-      }
-      __syncthreads();
-      float cs[CT], sn[CT];
-#pragma unroll
-      for (int ct = 0; ct < CT; ++ct)
-        phasor_turns(static_cast<double>(k0 + g) * xs[ct] * invL, &cs[ct], &sn[ct]);
-      const int remain = a.K - k0;
-      const int steps = remain >= kKC ? kKC / 2 : (remain + 1) / 2;
-      const float* rrow = re_s + cl * kCStride + g;
-      const float* irow = im_s + cl * kCStride + g;
-      for (int s = 0; s < steps; ++s) {
-        float ar[FT], ai[FT];
-#pragma unroll
-        for (int ft = 0; ft < FT; ++ft) {
-          ar[ft] = rrow[ft * 32 * kCStride + 2 * s];
-          ai[ft] = irow[ft * 32 * kCStride + 2 * s];
-        }
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct)
-#pragma unroll
-          for (int ft = 0; ft < FT; ++ft) {
-            acc[ct][ft] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[ft], cs[ct], acc[ct][ft], 0, 0, 0);
-            acc[ct][ft] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[ft], sn[ct], acc[ct][ft], 0, 0, 0);
-          }
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct) {
-          const float c2 = cs[ct] * rc[ct] - sn[ct] * rs[ct];
-          const float s2 = cs[ct] * rs[ct] + sn[ct] * rc[ct];
-          cs[ct] = c2;
-          sn[ct] = s2;
-        }
-      }
-    }
+  stage_bins(a, runs[0], ps0, f0, nrows, wave, lane);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  for (int ri = 0; ri < a.n_runs; ri += 2) {
+    const LagRun r0 = runs[ri];
+    const LagRun r1 = runs[ri + 1];
+    stage_bins(a, r1, ps1, f0, nrows, wave, lane);
+    conv_run<CT, FT>(a, mic, pairs, r0, st, ps0, cl, g, acc);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (ri + 2 < a.n_runs) stage_bins(a, runs[ri + 2], ps0, f0, nrows, wave, lane);
+    conv_run<CT, FT>(a, mic, pairs, r1, st, ps1, cl, g, acc);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
   }
 
 #pragma unroll
@@ -161,7 +238,7 @@ __global__ __launch_bounds__(256) void conventional_f32_kernel(ConvArgs a) {
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
         const int64_t ci = jb + ct * 32 + cl;
-        const float v = 2.0f * acc[ct][ft][r];
+        const float v = 4.0f * acc[ct][ft][r];
         if (ci < a.J && fg < a.F) {
           if (a.map) a.map[(size_t)fg * a.J + ci] = v;
           const unsigned long long k = peak_key(v, static_cast<unsigned>(ci));
@@ -201,7 +278,7 @@ __global__ __launch_bounds__(256) void conventional_f64_kernel(ConvArgs a) {
   for (int f = 0; f < kFB64; ++f) acc[f] = 0.0;
   for (int p = 0; p < a.P; ++p) {
     const PairDesc pd = a.pairs[p];
-    const double xsv = pair_xs(a, pd, qx, qy, qz);
+    const double xsv = pair_xs(a, a.mic, pd, qx, qy, qz);
     for (int k0 = 0; k0 < a.K; k0 += kKC) {
       __syncthreads();
       for (int e = tid; e < kFB64 * kKC; e += 256) {
@@ -256,6 +333,8 @@ hipError_t launch_conventional(const srp_geometry_s* g, const float2* psi, int F
   a.cand = g->d_cand;
   a.mic = g->d_mic;
   a.pairs = g->d_pairs;
+  a.runs = g->d_conv_runs;
+  a.n_runs = static_cast<int>(g->conv_runs.size());
   a.P = g->info.P;
   a.psi = psi;
   a.binw = g->d_binw;
@@ -268,10 +347,11 @@ hipError_t launch_conventional(const srp_geometry_s* g, const float2* psi, int F
   a.map = map;
   a.keys = keys;
   if (dtype == SRP_FP32) {
-    constexpr int CT = 2, FT = 2;
+    constexpr int CT = 2, FT = 4;
     constexpr int JB = 4 * 32 * CT, FB = 32 * FT;
     dim3 grid(static_cast<unsigned>((a.J + JB - 1) / JB), (F + FB - 1) / FB);
-    hipLaunchKernelGGL((conventional_f32_kernel<CT, FT>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((conventional_f32_kernel<CT, FT>), grid, dim3(256), 0, s, a, a.mic,
+                       a.pairs, a.runs);
     return hipGetLastError();
   }
   if (dtype == SRP_FP64) {

@@ -62,31 +62,184 @@ __device__ __forceinline__ double pair_x(const NyqArgs& a, const PairDesc& pd, d
   return (sqrt(ax * ax + ay * ay + az * az) - sqrt(bx * bx + by * by + bz * bz)) * a.inv_cT;
 }
 
+// sin(pi x) / pi for |x| <= 1/2: Taylor series of sin in float64,
+// x * sum_k (-1)^k pi^(2k) x^(2k) / (2k+1)!, truncated after x^17 (relative
+// truncation error < 1e-12 on the interval), then rounded once to float32.
+__device__ __forceinline__ float sinpi_over_pi(double x) {
+  const double u = x * x;
+  double p = 2.531217404137026e-07;  //  pi^16 / 17!
+  p = fma(p, u, -6.975873661656377e-06);  // -pi^14 / 15!
+  p = fma(p, u, 0.00014842879303107092);  //  pi^12 / 13!
+  p = fma(p, u, -0.0023460810354558226);  // -pi^10 / 11!
+  p = fma(p, u, 0.02614784781765479);  //  pi^8 / 9!
+  p = fma(p, u, -0.1907518241220842);  // -pi^6 / 7!
+  p = fma(p, u, 0.8117424252833535);  //  pi^4 / 5!
+  p = fma(p, u, -1.6449340668482264);  // -pi^2 / 3!
+  p = fma(p, u, 1.0);  // 1
+  return static_cast<float>(x * p);
+}
+
+// Issues the asynchronous copy of one lag run of the samples into an LDS
+// tile [frame][lag] (row stride kStride): wave w copies rows w, w + 4, ...
+// below nrows = min(FB, F - f0), one lane per lag. Lanes past the run copy the
+// run's last element, so those slots hold finite values (they meet a zero
+// weight). Rows at or past F are not copied: each output frame depends only
+// on its own row, and outputs of such frames are discarded.
+__device__ __forceinline__ void stage_run(const NyqArgs& a, const LagRun& run, int off,
+                                          float* tile, int f0, int nrows, int wave, int lane) {
+  typedef __attribute__((address_space(3))) void* lds_ptr;
+  if (run.len <= 0) return;
+  const int t = lane < run.len ? lane : run.len - 1;
+  const float* src = a.xi + (size_t)(f0 + wave) * a.S + off + run.t0 + t;
+  const size_t step = 4 * (size_t)a.S;
+  float* dst = tile + wave * kStride;
+  for (int f = wave; f < nrows; f += 4) {
+    __builtin_amdgcn_global_load_lds(src, (lds_ptr)dst, 4, 0, 0);
+    src += step;
+    dst += 4 * kStride;
+  }
+}
+
+// Per-lane state of the FP32 kernel's candidates for the current pair.
+template <int CT>
+struct LaneState {
+  double qx[CT], qy[CT], qz[CT];  // candidate (float64)
+  double rm[CT];                  // ||q - p_m|| for the current m (near field)
+  int xr[CT];                     // rint(x)
+  float xf[CT];                   // x - rint(x)
+  float sp[CT];                   // sin(pi xf) / pi
+  int cur_m, cur_p;
+};
+
+// Contracts one staged lag run (tile = samples [frame][lag]) into acc.
 template <int CT, int FT>
-__global__ __launch_bounds__(256) void nyquist_f32_kernel(NyqArgs a) {
+__device__ __forceinline__ void nyq_run(const NyqArgs& a, const double* __restrict__ mic,
+                                        const LagRun& run, const PairDesc& pd, LaneState<CT>& st,
+                                        const float* tile, int cl, int g,
+                                        floatx16 (&acc)[CT][FT]) {
+  if (run.p != st.cur_p) {
+    st.cur_p = run.p;
+    const double* pm = mic + 3 * pd.m;
+    const double* pn = mic + 3 * pd.mp;
+    const bool new_m = pd.m != st.cur_m;
+    st.cur_m = pd.m;
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      double x;
+      if (a.far_field) {
+        x = ((pm[0] - pn[0]) * st.qx[ct] + (pm[1] - pn[1]) * st.qy[ct] +
+             (pm[2] - pn[2]) * st.qz[ct]) * a.inv_cT;
+      } else {
+        if (new_m) {
+          const double ax = st.qx[ct] - pm[0], ay = st.qy[ct] - pm[1], az = st.qz[ct] - pm[2];
+          st.rm[ct] = sqrt(ax * ax + ay * ay + az * az);
+        }
+        const double bx = st.qx[ct] - pn[0], by = st.qy[ct] - pn[1], bz = st.qz[ct] - pn[2];
+        x = (st.rm[ct] - sqrt(bx * bx + by * by + bz * bz)) * a.inv_cT;
+      }
+      const double r = rint(x);
+      double f = x - r;
+      f = fabs(f) < 1e-30 ? 1e-30 : f;
+      st.xr[ct] = static_cast<int>(r);
+      st.xf[ct] = static_cast<float>(f);
+      st.sp[ct] = sinpi_over_pi(f);
+    }
+  }
+  // this lane's first lag in the run: n = -h + t0 + g
+  float dnum[CT], qv[CT];
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+    const int ia = st.xr[ct] + pd.h - run.t0 - g;
+    dnum[ct] = static_cast<float>(ia);
+    qv[ct] = (ia & 1) ? -st.sp[ct] : st.sp[ct];
+  }
+  const float* arow = tile + cl * kStride + g;
+  const int steps = (run.len + 1) >> 1;
+  // software pipeline, two steps per iteration with ping-pong operand sets:
+  // the LDS samples and weights of the next step are fetched and formed while
+  // the matrix cores work on the current one
+  float av0[FT], av1[FT], w0[CT], w1[CT];
+  auto fetch = [&](int s, float (&av)[FT], float (&w)[CT]) {
+    const int sc = s < steps ? s : steps - 1;
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft) av[ft] = arow[ft * 32 * kStride + 2 * sc];
+    const bool live = 2 * s + g < run.len;
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      const float wv = qv[ct] * __builtin_amdgcn_rcpf(dnum[ct] + st.xf[ct]);
+      w[ct] = live ? wv : 0.0f;
+      dnum[ct] -= 2.0f;
+    }
+  };
+  auto contract = [&](const float (&av)[FT], const float (&w)[CT]) {
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int ft = 0; ft < FT; ++ft)
+        acc[ct][ft] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[ft], w[ct], acc[ct][ft], 0, 0, 0);
+  };
+  auto order = [&]() {
+    // issue order: one matrix-core instruction (its operands were read a
+    // half-iteration earlier), then the next step's LDS reads, then the other
+    // matrix-core instructions with the weight arithmetic slotted between them
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x100, FT, 0);
+#pragma unroll
+    for (int i = 1; i < CT * FT; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    }
+  };
+  fetch(0, av0, w0);
+  int s = 0;
+  for (; s + 1 < steps; s += 2) {
+    fetch(s + 1, av1, w1);
+    contract(av0, w0);
+    order();
+    fetch(s + 2, av0, w0);
+    contract(av1, w1);
+    order();
+  }
+  if (s < steps) contract(av0, w0);
+}
+
+template <int CT, int FT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void nyquist_f32_kernel(NyqArgs a, const double* __restrict__ mic,
+                        const PairDesc* __restrict__ pairs, const LagRun* __restrict__ runs) {
   constexpr int FB = 32 * FT;
   constexpr int JW = 32 * CT;
   constexpr int JB = 4 * JW;
-  __shared__ float xs[FB * kStride];
+  // two staging tiles as distinct objects: the copy into one never aliases
+  // the reads of the other, so reads wait only on their own tile's copy
+  __shared__ float xs0[FB * kStride];
+  __shared__ float xs1[FB * kStride];
   __shared__ unsigned long long kbest[FB];
 
   const int tid = threadIdx.x;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
   const int cl = lane & 31;
   const int g = lane >> 5;
   const int64_t jb = (int64_t)blockIdx.x * JB + wave * JW;
   const int f0 = blockIdx.y * FB;
+  const int nrows = a.F - f0 < FB ? a.F - f0 : FB;
 
-  double qx[CT], qy[CT], qz[CT];
+  LaneState<CT> st;
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) {
     int64_t ci = jb + ct * 32 + cl;
     ci = ci < a.J ? ci : a.J - 1;
-    qx[ct] = a.cand[ci];
-    qy[ct] = a.cand[a.J + ci];
-    qz[ct] = a.cand[2 * a.J + ci];
+    st.qx[ct] = a.cand[ci];
+    st.qy[ct] = a.cand[a.J + ci];
+    st.qz[ct] = a.cand[2 * a.J + ci];
+    st.rm[ct] = 0.0;
+    st.xr[ct] = 0;
+    st.xf[ct] = 0.0f;
+    st.sp[ct] = 0.0f;
   }
+  st.cur_m = -1;
+  st.cur_p = -1;
   for (int i = tid; i < FB; i += 256) kbest[i] = 0ull;
 
   floatx16 acc[CT][FT];
@@ -97,54 +250,34 @@ __global__ __launch_bounds__(256) void nyquist_f32_kernel(NyqArgs a) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[ct][ft][r] = 0.0f;
 
-  for (int ri = 0; ri < a.n_runs; ++ri) {
-    const LagRun run = a.runs[ri];
-    const PairDesc pd = a.pairs[run.p];
-    const int len_pad = (run.len + 1) & ~1;
-    __syncthreads();
-    // stage samples [frame][lag] (zero past the run and past F)
-    const float* src = a.xi + pd.off + run.t0;
-    for (int f = wave; f < FB; f += 4) {
-      const int fg = f0 + f;
-      for (int t = lane; t < len_pad; t += 64) {
-        float v = 0.0f;
-        if (fg < a.F && t < run.len) v = src[(size_t)fg * a.S + t];
-        xs[f * kStride + t] = v;
-      }
-    }
-    __syncthreads();
+  {
+    const LagRun r0 = runs[0];
+    stage_run(a, r0, pairs[r0.p].off, xs0, f0, nrows, wave, lane);
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
 
-    float dnum[CT], frac[CT], qv[CT];
-    const int n_first = -pd.h + run.t0 + g;  // this lane's first lag in the run
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct) {
-      const double x = pair_x(a, pd, qx[ct], qy[ct], qz[ct]);
-      const double xr = rint(x);
-      float xf = static_cast<float>(x - xr);
-      xf = fabsf(xf) < 1e-30f ? 1e-30f : xf;
-      const int ia = static_cast<int>(xr) - n_first;
-      const float sgn = (ia & 1) ? -1.0f : 1.0f;
-      qv[ct] = sgn * sinpif(xf) * 0.318309886183790671538f;
-      dnum[ct] = static_cast<float>(ia);
-      frac[ct] = xf;
+  for (int ri = 0; ri < a.n_runs; ri += 2) {
+    {  // even run: read xs0, copy the next run into xs1
+      const LagRun run = runs[ri];
+      const PairDesc pd = pairs[run.p];
+      const LagRun nx = runs[ri + 1];
+      const int nx_off = pairs[nx.p].off;
+      stage_run(a, nx, nx_off, xs1, f0, nrows, wave, lane);
+      nyq_run<CT, FT>(a, mic, run, pd, st, xs0, cl, g, acc);
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
     }
-    const float* arow = xs + cl * kStride + g;
-    const int steps = len_pad >> 1;
-    for (int s = 0; s < steps; ++s) {
-      float w[CT];
-#pragma unroll
-      for (int ct = 0; ct < CT; ++ct) {
-        w[ct] = qv[ct] * __builtin_amdgcn_rcpf(dnum[ct] + frac[ct]);
-        dnum[ct] -= 2.0f;
+    {  // odd run: read xs1, copy the next run into xs0 (n_runs is even)
+      const LagRun run = runs[ri + 1];
+      const PairDesc pd = pairs[run.p];
+      if (ri + 2 < a.n_runs) {
+        const LagRun nx = runs[ri + 2];
+        stage_run(a, nx, pairs[nx.p].off, xs0, f0, nrows, wave, lane);
       }
-      float av[FT];
-#pragma unroll
-      for (int ft = 0; ft < FT; ++ft) av[ft] = arow[ft * 32 * kStride + 2 * s];
-#pragma unroll
-      for (int ct = 0; ct < CT; ++ct)
-#pragma unroll
-        for (int ft = 0; ft < FT; ++ft)
-          acc[ct][ft] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[ft], w[ct], acc[ct][ft], 0, 0, 0);
+      nyq_run<CT, FT>(a, mic, run, pd, st, xs1, cl, g, acc);
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
     }
   }
 
@@ -264,10 +397,11 @@ hipError_t launch_nyquist(const srp_geometry_s* g, const float* xi, int F, int d
   a.map = map;
   a.keys = keys;
   if (dtype == SRP_FP32) {
-    constexpr int CT = 2, FT = 2;
+    constexpr int CT = 2, FT = 4;
     constexpr int JB = 4 * 32 * CT, FB = 32 * FT;
     dim3 grid(static_cast<unsigned>((a.J + JB - 1) / JB), (F + FB - 1) / FB);
-    hipLaunchKernelGGL((nyquist_f32_kernel<CT, FT>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((nyquist_f32_kernel<CT, FT>), grid, dim3(256), 0, s, a, a.mic, a.pairs,
+                       a.runs);
     return hipGetLastError();
   }
   if (dtype == SRP_FP64) {

@@ -96,6 +96,7 @@ void free_geometry(srp_geometry_s* g) {
   hipFree(g->d_pairs);
   hipFree(g->d_gcc_tiles);
   hipFree(g->d_nyq_runs);
+  hipFree(g->d_conv_runs);
   hipFree(g->d_window);
   hipFree(g->d_twiddle);
   hipFree(g->d_gcc_table);
@@ -205,6 +206,13 @@ srp_status srp_geometry(const double* mic_xyz, int32_t M, const double* cand_xyz
     for (int t0 = 0; t0 < W; t0 += kNyqRunMax)
       g->nyq_runs.push_back(LagRun{p, t0, W - t0 < kNyqRunMax ? W - t0 : kNyqRunMax, 0});
   }
+  // the FP32 interpolation kernel consumes runs two at a time: pad with an
+  // empty run of the last pair (no lags, no copy, no pair change)
+  if (g->nyq_runs.size() % 2) g->nyq_runs.push_back(LagRun{P - 1, 2 * (np[P - 1] + n_aux) + 1, 0, 0});
+  for (int p = 0; p < P; ++p)
+    for (int k0 = 0; k0 < in.K; k0 += kConvRunBins)
+      g->conv_runs.push_back(LagRun{p, k0, in.K - k0 < kConvRunBins ? in.K - k0 : kConvRunBins, 0});
+  if (g->conv_runs.size() % 2) g->conv_runs.push_back(LagRun{P - 1, in.K, 0, 0});
   const int K = in.K;
   g->gcc_nw = 2 * h_max + 1 + kGccLagTile;
 
@@ -256,6 +264,7 @@ srp_status srp_geometry(const double* mic_xyz, int32_t M, const double* cand_xyz
   if (e == hipSuccess) e = upload(&g->d_pairs, g->pairs.data(), g->pairs.size(), s);
   if (e == hipSuccess) e = upload(&g->d_gcc_tiles, g->gcc_tiles.data(), g->gcc_tiles.size(), s);
   if (e == hipSuccess) e = upload(&g->d_nyq_runs, g->nyq_runs.data(), g->nyq_runs.size(), s);
+  if (e == hipSuccess) e = upload(&g->d_conv_runs, g->conv_runs.data(), g->conv_runs.size(), s);
   if (e == hipSuccess) e = upload(&g->d_window, win.data(), win.size(), s);
   if (e == hipSuccess) e = upload(&g->d_twiddle, tw.data(), tw.size(), s);
   if (e == hipSuccess) e = upload(&g->d_gcc_table, gtab.data(), gtab.size(), s);

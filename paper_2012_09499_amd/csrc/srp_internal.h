@@ -25,8 +25,11 @@ struct LagRun {
   int32_t p, t0, len, pad;
 };
 
-// Lag runs of the Nyquist interpolation kernels are at most this long (even).
-constexpr int kNyqRunMax = 128;
+// Lag runs of the Nyquist interpolation kernels are at most this long (one
+// lane per lag when a wave copies a run into LDS).
+constexpr int kNyqRunMax = 64;
+// Bin runs of the conventional kernel are at most this many bins.
+constexpr int kConvRunBins = 32;
 // Lag tiles of the GCC-sample kernel are 32 lags wide (one matrix-core tile).
 constexpr int kGccLagTile = 32;
 
@@ -43,13 +46,15 @@ struct srp_geometry_s {
   std::vector<int32_t> N_p;
   std::vector<int64_t> offsets;
   std::vector<srp::LagRun> gcc_tiles;  // lag tiles of srp_gcc_samples
-  std::vector<srp::LagRun> nyq_runs;   // lag runs of srp_map_nyquist
+  std::vector<srp::LagRun> nyq_runs;   // lag runs of srp_map_nyquist (even count)
+  std::vector<srp::LagRun> conv_runs;  // bin runs (p, k0, len) of srp_map_conventional (even count)
   // device copies
   double* d_mic = nullptr;             // [M][3]
   double* d_cand = nullptr;            // [3][J] (structure of arrays)
   srp::PairDesc* d_pairs = nullptr;    // [P]
   srp::LagRun* d_gcc_tiles = nullptr;
   srp::LagRun* d_nyq_runs = nullptr;
+  srp::LagRun* d_conv_runs = nullptr;
   float* d_window = nullptr;           // [L]
   float2* d_twiddle = nullptr;         // [L/2] exp(-j 2 pi t / L)
   float2* d_gcc_table = nullptr;       // [K][gcc_nw] (cos, -sin) of 2 pi f_k n T
