@@ -31,6 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3   # MI355X dense FP32 (matrix cores), published
+PEAK_BF16_TFLOPS = 2500.0  # MI355X dense BF16 / FP16 (matrix cores), published
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_nyquist_f32_cfg2.json")
 
@@ -127,16 +128,16 @@ def main():
     frames = torch.from_numpy(wl.frames).to(dev)
     stream = torch.cuda.current_stream()
 
-    def nyquist_step(ev=None):
+    def nyquist_step(ev=None, dtype="fp32"):
         if ev is not None:
             ev[0].record(stream)
         psi = srp.cross_spectra(g, frames, out=pipe.psi, workspace=pipe.workspace)
         if ev is not None:
             ev[1].record(stream)
-        xi = srp.gcc_samples(g, psi, out=pipe.xi)
+        xi = srp.gcc_samples(g, psi, out=pipe.samples_buffer(dtype), dtype=dtype)
         if ev is not None:
             ev[2].record(stream)
-        srp.map_nyquist(g, xi, want_map=False, peaks_out=pipe.peaks)
+        srp.map_nyquist(g, xi, dtype=dtype, want_map=False, peaks_out=pipe.peaks)
         if ev is not None:
             ev[3].record(stream)
 
@@ -159,8 +160,9 @@ def main():
     print(f"[bench] nyquist fp32: {ms_step:.3f} ms/step (spectra {t_spec:.3f}, gcc {t_gcc:.3f}, "
           f"map {t_map:.3f} ms)", file=sys.stderr, flush=True)
 
-    flops_map = 2.0 * g.S * wl.J * wl.F          # 2 N P J per frame (Eq. SRPapproxcompR)
-    flops_gcc = 4.0 * g.S * g.K * wl.F           # N P K complex MACs, real part (Eq. SRPapproxcompC)
+    NP = g.W_total                               # N P samples per frame (Sec. 3.3)
+    flops_map = 2.0 * NP * wl.J * wl.F           # 2 N P J per frame (Eq. SRPapproxcompR)
+    flops_gcc = 4.0 * NP * g.K * wl.F            # N P K complex MACs, real part (Eq. SRPapproxcompC)
     achieved = flops_map / (t_map * 1e-3) / 1e12
     traffic = load_traffic(flops_map)
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
@@ -175,11 +177,34 @@ def main():
            "scaling": "weak", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic (seeded free-field white-noise sources, 10 dB sensor noise)",
            "config": {"workload": wl.name, "M": wl.M, "P": wl.P, "J": wl.J, "F": wl.F,
-                      "L": wl.L, "K": g.K, "fs": wl.fs, "n_aux": wl.n_aux, "S": g.S,
-                      "N_avg_samples_per_pair": g.S / wl.P},
+                      "L": wl.L, "K": g.K, "fs": wl.fs, "n_aux": wl.n_aux,
+                      "samples_per_frame_NP": NP, "N_avg_samples_per_pair": NP / wl.P},
            "roofline": roofline,
            "kernels_ms": {"cross_spectra": t_spec, "gcc_samples": t_gcc, "map_nyquist": t_map},
            "gcc_samples_tflops": flops_gcc / (t_gcc * 1e-3) / 1e12}
+
+    # low-precision Nyquist beside FP32 (same frames, same step structure)
+    ref_pk = srp.decode_peaks(pipe.peaks)[0].copy()
+    for dt in ("bf16", "fp16"):
+        nyquist_step(dtype=dt)
+        torch.cuda.synchronize()
+        evl = [[torch.cuda.Event(enable_timing=True) for _ in range(4)]
+               for _ in range(args.steps)]
+        l0 = time.perf_counter()
+        for k in range(args.steps):
+            nyquist_step(evl[k], dtype=dt)
+        torch.cuda.synchronize()
+        ms_l = (time.perf_counter() - l0) * 1e3 / args.steps
+        t_map_l = float(np.mean([e[2].elapsed_time(e[3]) for e in evl]))
+        pk_l = srp.decode_peaks(pipe.peaks)[0]
+        ach = flops_map / (t_map_l * 1e-3) / 1e12
+        out[f"nyquist_{dt}"] = {
+            "value": evals / (ms_l * 1e-3), "unit": "cand-pair evals/s", "ms_per_step": ms_l,
+            "map_kernel_ms": t_map_l, "achieved_tflops": ach, "peak_tflops": PEAK_BF16_TFLOPS,
+            "frac": ach / PEAK_BF16_TFLOPS, "speedup_vs_fp32": ms_step / ms_l,
+            "argmax_agree_with_fp32": float(np.mean(pk_l == ref_pk))}
+        print(f"[bench] nyquist {dt}: {ms_l:.3f} ms/step (map {t_map_l:.3f} ms, {ach:.0f} TFLOP/s)",
+              file=sys.stderr, flush=True)
 
     if not args.no_conventional:
         def conv_step():
@@ -196,19 +221,26 @@ def main():
         out["conventional"] = {"value": evals / (ms_conv * 1e-3), "unit": "cand-pair evals/s",
                                "ms_per_step": ms_conv, "steps": args.conv_steps,
                                "algorithmic_tflops": flops_conv / (ms_conv * 1e-3) / 1e12,
-                               "nyquist_speedup": ms_conv / ms_step}
+                               "nyquist_speedup": ms_conv / ms_step,
+                               "argmax_agree_with_nyquist_fp32":
+                                   float(np.mean(srp.decode_peaks(pipe.peaks)[0] == ref_pk))}
         print(f"[bench] conventional fp32: {ms_conv:.1f} ms/step", file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:
         cb, idx, ref = cpu_baseline(wl, args.cpu_candidates)
         out["cpu_baseline"] = cb
         # parity of the timed configuration on the sampled candidates (not timed)
+        del pipe
         keep = srp.SrpPipeline(g, wl.F, device=dev, keep_map=True)
-        m, pk = keep.nyquist(frames)
-        sub = m[:, torch.from_numpy(idx).to(dev)].cpu().numpy().astype(np.float64)
-        err = np.sqrt(((sub - ref) ** 2).sum(1) / (ref ** 2).sum(1))
-        out["parity_sampled"] = {"candidates": int(idx.size), "max_rel_err": float(err.max()),
-                                 "median_rel_err": float(np.median(err))}
+        sel = torch.from_numpy(idx).to(dev)
+        out["parity_sampled"] = {"candidates": int(idx.size)}
+        for dt in ("fp32", "bf16", "fp16"):
+            m, _ = keep.nyquist(frames, dtype=dt)
+            sub = m[:, sel].cpu().numpy().astype(np.float64)
+            e = np.sqrt(((sub - ref) ** 2).sum(1) / (ref ** 2).sum(1))
+            out["parity_sampled"][dt] = {"max_rel_err": float(e.max()),
+                                         "median_rel_err": float(np.median(e))}
+        err = np.asarray([out["parity_sampled"]["fp32"]["max_rel_err"]])
         print(f"[bench] cpu baseline {cb['value']:.3e} evals/s on {cb['cores']} BLAS threads "
               f"({cb['seconds']:.1f}s); sampled map rel err max {err.max():.2e}",
               file=sys.stderr, flush=True)

@@ -29,9 +29,11 @@
  *   half-width h_p = N_p + N_aux with N_p = floor(d_p / (c T)) evaluated in
  *   float64 exactly in that order, d_p = ||p_m - p_m'||; the window holds
  *   W_p = 2 h_p + 1 lags n = -h_p .. h_p (Eq. SRPapprox, Section 3.3).
- * - Packed GCC samples: sample (p, n) of a frame sits at column
- *   offset_p + (n + h_p), offset_0 = 0, offset_{p+1} = offset_p + W_p,
- *   S = offset_P.
+ * - GCC-sample layout: sample (p, n) of a frame sits at column
+ *   offset_p + (n + h_p); offset_0 = 0 and offset_{p+1} = offset_p + W_p
+ *   rounded up to a multiple of 8 (the up to 7 columns after each window are
+ *   zeros), S = offset_P. Windows start at multiples of 8 samples so that
+ *   16-byte copies of bf16/fp16 samples stay aligned.
  */
 #ifndef SRP_H
 #define SRP_H
@@ -85,7 +87,7 @@ typedef struct srp_geometry_s srp_geometry_t;
 typedef struct {
   int32_t M, P, L, K;      /* mics, pairs, frame length, one-sided bins            */
   int64_t J;               /* candidates                                            */
-  int64_t S;               /* packed GCC samples per frame                          */
+  int64_t S;               /* GCC-sample columns per frame (layout above)           */
   int32_t h_max;           /* max_p h_p                                             */
   int32_t n_aux;
   int32_t field, window;
@@ -93,8 +95,8 @@ typedef struct {
 } srp_geometry_info;
 
 /* Host-only pair layout (Section 3.2, 3.3): computes h_p - n_aux = N_p for
- * every pair (into N_p, P entries, may be NULL), the packed offsets (P + 1
- * entries, may be NULL) and S (may be NULL). mic_xyz: host, M x 3 float64,
+ * every pair (into N_p, P entries, may be NULL), the sample-layout offsets
+ * (P + 1 entries, may be NULL) and S (may be NULL). mic_xyz: host, M x 3 float64,
  * metres, row-major. Requires M >= 2, c > 0, f_max > 0, n_aux >= 0. Touches
  * no device. */
 srp_status srp_pair_layout(const double* mic_xyz, int32_t M, double c, double f_max,
@@ -139,11 +141,13 @@ srp_status srp_cross_spectra(const srp_geometry_t* g, const float* frames, int32
 
 /* GCC samples at the critical lags (Section 3.2, first step; cost Eq.
  * SRPapproxcompC): xi[f][offset_p + n + h_p] = xi_p(n T) for |n| <= h_p.
- *   psi  device, F x P x K complex64 as written by srp_cross_spectra
- *   xi   device, F x S float32, written
- * dtype: SRP_FP32 (the only type for this call). */
+ *   psi    device, F x P x K complex64 as written by srp_cross_spectra
+ *   dtype  storage type of xi: SRP_FP32 (float), SRP_BF16 (bfloat16) or
+ *          SRP_FP16 (IEEE half). The sum is accumulated in float32 and rounded
+ *          once to the storage type.
+ *   xi     device, F x S elements of that type, written */
 srp_status srp_gcc_samples(const srp_geometry_t* g, const float* psi, int32_t F, int32_t dtype,
-                           float* xi, void* stream);
+                           void* xi, void* stream);
 
 /* Conventional SRP map (Eq. SRP_T_IFT with one discrete IFT per candidate,
  * pair and bin, Section 2.4): map[f][i] = 2 sum_p xi_p(dt_p(i)).
@@ -160,11 +164,15 @@ srp_status srp_map_conventional(const srp_geometry_t* g, const float* psi, int32
  * sinc(x) = sin(pi x) / (pi x), sinc(0) = 1. TDOAs are formed on the fly in
  * float64; sinc weights are formed from the float64 argument split into an
  * integer and a float32 fraction.
- *   xi     device, F x S float32 (srp_gcc_samples layout)
+ *   xi     device, F x S samples in the srp_gcc_samples layout, stored as
+ *          float for SRP_FP32 and SRP_FP64, bfloat16 for SRP_BF16, half for
+ *          SRP_FP16 (srp_gcc_samples with the same dtype writes them)
+ *   dtype  SRP_FP32: float32 matrix cores; SRP_BF16 / SRP_FP16: weights and
+ *          samples in that type on the matrix cores, float32 accumulation;
+ *          SRP_FP64: float64 vector units (an exactness check, not a fast path)
  *   map    device, F x J float32, written; may be NULL if peaks is not
- *   peaks  device, F srp_peak, written; may be NULL if map is not
- * dtype: SRP_FP32, SRP_BF16, SRP_FP16 or SRP_FP64. */
-srp_status srp_map_nyquist(const srp_geometry_t* g, const float* xi, int32_t F, int32_t dtype,
+ *   peaks  device, F srp_peak, written; may be NULL if map is not */
+srp_status srp_map_nyquist(const srp_geometry_t* g, const void* xi, int32_t F, int32_t dtype,
                            float* map, srp_peak* peaks, void* stream);
 
 /* Per-frame argmax of a map (Section 2.2), lowest index on ties.

@@ -6,5 +6,6 @@ include/srp.h); this package is its thin Python binding plus a frame
 pipeline helper.
 """
 from ._lib import (DTYPES, EXPORTS, Geometry, SrpError, argmax, cross_spectra, decode_peaks,  # noqa: F401
-                   gcc_samples, lib, map_conventional, map_nyquist, pair_layout, version)
+                   gcc_samples, lib, map_conventional, map_nyquist, pair_layout,
+                   sample_torch_dtype, unpack_samples, version)
 from .pipeline import SrpPipeline  # noqa: F401

@@ -17,6 +17,13 @@ LIB_PATH = os.path.join(_PKG, "libsrp.so")
 
 SRP_OK, SRP_ERR_INVALID_ARG, SRP_ERR_OUT_OF_MEMORY, SRP_ERR_DEVICE, SRP_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
 DTYPES = {"fp32": 0, "bf16": 1, "fp16": 2, "fp64": 3}
+
+
+def sample_torch_dtype(dtype: str):
+    """Storage type of GCC samples for a map dtype (fp64 maps read float32 samples)."""
+    import torch
+    return {"fp32": torch.float32, "fp64": torch.float32, "bf16": torch.bfloat16,
+            "fp16": torch.float16}[dtype]
 FIELDS = {"near": 0, "far": 1}
 WINDOWS = {"hann": 0, "sqrt_hann": 1, "rect": 2}
 PHAT = 0
@@ -143,6 +150,9 @@ class Geometry:
         self.J, self.S, self.h_max, self.n_aux = info.J, info.S, info.h_max, info.n_aux
         self.fs, self.c, self.f_max, self.T = info.fs, info.c, info.f_max, info.T
         self.field = field
+        # samples per frame without the layout's alignment gaps (N P of Sec. 3.3)
+        self.W = 2 * (self.N_p.astype(np.int64) + self.n_aux) + 1
+        self.W_total = int(self.W.sum())
 
     @property
     def handle(self):
@@ -187,16 +197,25 @@ def cross_spectra(g: Geometry, frames, out=None, workspace=None, stream=None):
 
 
 def gcc_samples(g: Geometry, psi, out=None, dtype: str = "fp32", stream=None):
-    """psi [F][P][K] complex64 -> xi [F][S] float32 (srp_gcc_samples)."""
+    """psi [F][P][K] complex64 -> xi [F][S] (float32, bfloat16 or float16) (srp_gcc_samples)."""
     import torch
     _need_cuda(psi, "psi", torch.complex64)
     F = psi.shape[0]
+    tdt = sample_torch_dtype(dtype)
     if out is None:
-        out = torch.empty((F, g.S), dtype=torch.float32, device=psi.device)
-    _need_cuda(out, "xi", torch.float32, (F, g.S))
-    _check(lib().srp_gcc_samples(g.handle, psi.data_ptr(), F, DTYPES[dtype], out.data_ptr(),
-                                 _stream_handle(stream)))
+        out = torch.empty((F, g.S), dtype=tdt, device=psi.device)
+    _need_cuda(out, "xi", tdt, (F, g.S))
+    _check(lib().srp_gcc_samples(g.handle, psi.data_ptr(), F, DTYPES[dtype if dtype != "fp64" else "fp32"],
+                                 out.data_ptr(), _stream_handle(stream)))
     return out
+
+
+def unpack_samples(g: Geometry, xi):
+    """Host copy of xi without the alignment gaps: [F][sum_p W_p] float64, pair-major."""
+    h = xi.detach().float().cpu().numpy().astype(np.float64)
+    cols = np.concatenate([np.arange(int(o), int(o) + int(w))
+                           for o, w in zip(g.offsets[:-1], g.W)])
+    return h[:, cols]
 
 
 def _map_outputs(g, F, device, want_map, want_peaks, map_out, peaks_out):
@@ -216,9 +235,11 @@ def _map_outputs(g, F, device, want_map, want_peaks, map_out, peaks_out):
 
 def map_nyquist(g: Geometry, xi, dtype: str = "fp32", want_map: bool = True,
                 want_peaks: bool = True, map_out=None, peaks_out=None, stream=None):
-    """xi [F][S] -> (map [F][J] float32 | None, peaks [F][2] int64 | None) (srp_map_nyquist)."""
-    import torch
-    _need_cuda(xi, "xi", torch.float32)
+    """xi [F][S] -> (map [F][J] float32 | None, peaks [F][2] int64 | None) (srp_map_nyquist).
+
+    xi must be stored in the type srp_gcc_samples writes for `dtype`.
+    """
+    _need_cuda(xi, "xi", sample_torch_dtype(dtype))
     F = xi.shape[0]
     if xi.shape[1] != g.S:
         raise ValueError(f"xi must be [F][{g.S}]")

@@ -17,6 +17,8 @@ namespace srp {
 namespace {
 
 constexpr int kKC = 32;          // bins per staged run (16 steps)
+// Above this many terms (2 K P) per map value the FP32 kernel sums in two levels.
+constexpr int64_t kConvPlainSumMax = 262144;
 constexpr int kCStride = 2 * kKC + 1;  // LDS row stride (odd): interleaved re, im
 
 struct ConvArgs {
@@ -38,6 +40,9 @@ struct ConvArgs {
   unsigned long long* keys;
 };
 
+// x_s = dt fs for the candidate (qx, qy, qz), float64. `exact` selects the
+// correctly rounded square root (the float64 exactness kernel) over norm3.
+template <bool exact = false>
 __device__ __forceinline__ double pair_xs(const ConvArgs& a, const double* __restrict__ mic,
                                           const PairDesc& pd, double qx, double qy, double qz) {
   const double* pm = mic + 3 * pd.m;
@@ -47,7 +52,9 @@ __device__ __forceinline__ double pair_xs(const ConvArgs& a, const double* __res
   }
   const double ax = qx - pm[0], ay = qy - pm[1], az = qz - pm[2];
   const double bx = qx - pn[0], by = qy - pn[1], bz = qz - pn[2];
-  return (sqrt(ax * ax + ay * ay + az * az) - sqrt(bx * bx + by * by + bz * bz)) * a.fs_over_c;
+  if (exact)
+    return (sqrt(ax * ax + ay * ay + az * az) - sqrt(bx * bx + by * by + bz * bz)) * a.fs_over_c;
+  return (norm3(ax, ay, az) - norm3(bx, by, bz)) * a.fs_over_c;
 }
 
 // (cos, sin) of 2 pi v for v given in float64 turns, reduced mod 1 in float64.
@@ -168,7 +175,11 @@ __device__ __forceinline__ void conv_run(const ConvArgs& a, const double* __rest
 // mic, pairs and runs arrive as __restrict__ const kernel parameters so that
 // their uniform reads are scalar loads (they then never wait on the
 // asynchronous LDS copies in flight).
-template <int CT, int FT>
+// COMP: two-level summation (the matrix-core accumulator holds one pair's
+// 2K terms and is added into a second float32 accumulator when the pair
+// changes), for geometries where one float32 sum over all 2KP terms would
+// lose the 1e-5 map accuracy.
+template <int CT, int FT, bool COMP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void conventional_f32_kernel(ConvArgs a, const double* __restrict__ mic,
                              const PairDesc* __restrict__ pairs,
@@ -205,12 +216,33 @@ void conventional_f32_kernel(ConvArgs a, const double* __restrict__ mic,
   for (int i = tid; i < FB; i += 256) kbest[i] = 0ull;
 
   floatx16 acc[CT][FT];
+  floatx16 hi[COMP ? CT : 1][COMP ? FT : 1];
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
     for (int ft = 0; ft < FT; ++ft)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[ct][ft][r] = 0.0f;
+  if (COMP) {
+#pragma unroll
+    for (int ct = 0; ct < (COMP ? CT : 1); ++ct)
+#pragma unroll
+      for (int ft = 0; ft < (COMP ? FT : 1); ++ft)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) hi[ct][ft][r] = 0.0f;
+  }
+  auto fold = [&](const LagRun& run) {
+    if (COMP && run.len > 0 && run.p != st.cur_p && st.cur_p >= 0) {
+#pragma unroll
+      for (int ct = 0; ct < (COMP ? CT : 1); ++ct)
+#pragma unroll
+        for (int ft = 0; ft < (COMP ? FT : 1); ++ft) {
+          hi[ct][ft] += acc[ct][ft];
+#pragma unroll
+          for (int r = 0; r < 16; ++r) acc[ct][ft][r] = 0.0f;
+        }
+    }
+  };
 
   stage_bins(a, runs[0], ps0, f0, nrows, wave, lane);
   __builtin_amdgcn_s_waitcnt(0);
@@ -219,13 +251,22 @@ void conventional_f32_kernel(ConvArgs a, const double* __restrict__ mic,
     const LagRun r0 = runs[ri];
     const LagRun r1 = runs[ri + 1];
     stage_bins(a, r1, ps1, f0, nrows, wave, lane);
+    fold(r0);
     conv_run<CT, FT>(a, mic, pairs, r0, st, ps0, cl, g, acc);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (ri + 2 < a.n_runs) stage_bins(a, runs[ri + 2], ps0, f0, nrows, wave, lane);
+    fold(r1);
     conv_run<CT, FT>(a, mic, pairs, r1, st, ps1, cl, g, acc);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+  }
+
+  if (COMP) {
+#pragma unroll
+    for (int ct = 0; ct < (COMP ? CT : 1); ++ct)
+#pragma unroll
+      for (int ft = 0; ft < (COMP ? FT : 1); ++ft) acc[ct][ft] += hi[ct][ft];
   }
 
 #pragma unroll
@@ -278,7 +319,7 @@ __global__ __launch_bounds__(256) void conventional_f64_kernel(ConvArgs a) {
   for (int f = 0; f < kFB64; ++f) acc[f] = 0.0;
   for (int p = 0; p < a.P; ++p) {
     const PairDesc pd = a.pairs[p];
-    const double xsv = pair_xs(a, a.mic, pd, qx, qy, qz);
+    const double xsv = pair_xs<true>(a, a.mic, pd, qx, qy, qz);
     for (int k0 = 0; k0 < a.K; k0 += kKC) {
       __syncthreads();
       for (int e = tid; e < kFB64 * kKC; e += 256) {
@@ -347,11 +388,18 @@ hipError_t launch_conventional(const srp_geometry_s* g, const float2* psi, int F
   a.map = map;
   a.keys = keys;
   if (dtype == SRP_FP32) {
-    constexpr int CT = 2, FT = 4;
-    constexpr int JB = 4 * 32 * CT, FB = 32 * FT;
-    dim3 grid(static_cast<unsigned>((a.J + JB - 1) / JB), (F + FB - 1) / FB);
-    hipLaunchKernelGGL((conventional_f32_kernel<CT, FT>), grid, dim3(256), 0, s, a, a.mic,
-                       a.pairs, a.runs);
+    constexpr int FT = 4, FB = 32 * FT;
+    if (2 * (int64_t)a.K * a.P <= kConvPlainSumMax) {
+      constexpr int CT = 2, JB = 4 * 32 * CT;
+      dim3 grid(static_cast<unsigned>((a.J + JB - 1) / JB), (F + FB - 1) / FB);
+      hipLaunchKernelGGL((conventional_f32_kernel<CT, FT, false>), grid, dim3(256), 0, s, a,
+                         a.mic, a.pairs, a.runs);
+    } else {
+      constexpr int CT = 1, JB = 4 * 32 * CT;
+      dim3 grid(static_cast<unsigned>((a.J + JB - 1) / JB), (F + FB - 1) / FB);
+      hipLaunchKernelGGL((conventional_f32_kernel<CT, FT, true>), grid, dim3(256), 0, s, a,
+                         a.mic, a.pairs, a.runs);
+    }
     return hipGetLastError();
   }
   if (dtype == SRP_FP64) {

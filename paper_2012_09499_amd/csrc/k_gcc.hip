@@ -9,18 +9,19 @@
 // float32 matrix-core instruction v_mfma_f32_32x32x2f32: each step consumes
 // one bin (k2 = 0: real part, k2 = 1: imaginary part). The phase table holds
 // (cos, -sin) of 2 pi f_k n T, built in float64 on the host with the phase
-// reduced exactly mod 2 pi and rounded once.
+// reduced exactly mod 2 pi and rounded once. Samples accumulate in float32
+// and are stored as OutT (float, bf16 or fp16: one rounding).
 #include "srp_device.h"
 #include "srp_internal.h"
 
 namespace srp {
 namespace {
 
-template <int FT>
+template <int FT, typename OutT>
 __global__ __launch_bounds__(64) void gcc_samples_kernel(
     const float2* __restrict__ psi, const float* __restrict__ binw,
     const float2* __restrict__ table, int nw, int h_max, const LagRun* __restrict__ tiles,
-    const PairDesc* __restrict__ pairs, int F, int P, int K, int S, float* __restrict__ xi) {
+    const PairDesc* __restrict__ pairs, int F, int P, int K, int S, OutT* __restrict__ xi) {
   const LagRun tl = tiles[blockIdx.x];
   const PairDesc pd = pairs[tl.p];
   const int lane = threadIdx.x;
@@ -71,28 +72,48 @@ __global__ __launch_bounds__(64) void gcc_samples_kernel(
   }
 
   // D[frame][lag]: lane (cl, g), register r holds frame 8 (r / 4) + 4 g + r % 4, lag cl.
-  if (cl < tl.len) {
-    float* col = xi + pd.off + tl.t0 + cl;
+  // lags past the window up to the next multiple of kSampleAlign are the
+  // layout's gap: written as zeros (the window length 2h+1 is odd, so the gap
+  // of the last tile always fits in it)
+  const int W = 2 * pd.h + 1;
+  const int Wpad = (W + kSampleAlign - 1) / kSampleAlign * kSampleAlign;
+  const int tl_end = Wpad - tl.t0 < kGccLagTile ? Wpad - tl.t0 : kGccLagTile;
+  if (cl < tl_end) {
+    const bool real = cl < tl.len;
+    OutT* col = xi + pd.off + tl.t0 + cl;
 #pragma unroll
     for (int ft = 0; ft < FT; ++ft)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int f = fbase + ft * 32 + 8 * (r >> 2) + 4 * g + (r & 3);
-        if (f < F) col[(size_t)f * S] = acc[ft][r];
+        if (f < F) col[(size_t)f * S] = static_cast<OutT>(real ? acc[ft][r] : 0.0f);
       }
   }
 }
 
 }  // namespace
 
-hipError_t launch_gcc_samples(const srp_geometry_s* g, const float2* psi, int F, float* xi,
-                              hipStream_t s) {
+hipError_t launch_gcc_samples(const srp_geometry_s* g, const float2* psi, int F, int dtype,
+                              void* xi, hipStream_t s) {
   constexpr int FT = 2;
   const int n_tiles = static_cast<int>(g->gcc_tiles.size());
   dim3 grid(n_tiles, (F + 32 * FT - 1) / (32 * FT));
-  hipLaunchKernelGGL(gcc_samples_kernel<FT>, grid, dim3(64), 0, s, psi, g->d_binw,
-                     g->d_gcc_table, g->gcc_nw, g->info.h_max, g->d_gcc_tiles, g->d_pairs, F,
-                     g->info.P, g->info.K, static_cast<int>(g->info.S), xi);
+  const int S = static_cast<int>(g->info.S);
+  if (dtype == SRP_FP32) {
+    hipLaunchKernelGGL((gcc_samples_kernel<FT, float>), grid, dim3(64), 0, s, psi, g->d_binw,
+                       g->d_gcc_table, g->gcc_nw, g->info.h_max, g->d_gcc_tiles, g->d_pairs, F,
+                       g->info.P, g->info.K, S, static_cast<float*>(xi));
+  } else if (dtype == SRP_BF16) {
+    hipLaunchKernelGGL((gcc_samples_kernel<FT, __bf16>), grid, dim3(64), 0, s, psi, g->d_binw,
+                       g->d_gcc_table, g->gcc_nw, g->info.h_max, g->d_gcc_tiles, g->d_pairs, F,
+                       g->info.P, g->info.K, S, static_cast<__bf16*>(xi));
+  } else if (dtype == SRP_FP16) {
+    hipLaunchKernelGGL((gcc_samples_kernel<FT, _Float16>), grid, dim3(64), 0, s, psi, g->d_binw,
+                       g->d_gcc_table, g->gcc_nw, g->info.h_max, g->d_gcc_tiles, g->d_pairs, F,
+                       g->info.P, g->info.K, S, static_cast<_Float16*>(xi));
+  } else {
+    return hipErrorNotSupported;
+  }
   return hipGetLastError();
 }
 

@@ -33,6 +33,11 @@ namespace {
 
 constexpr int kStride = kNyqRunMax + 1;  // LDS row stride (odd) of the [frame][lag] tile
 
+// Above this many samples per frame the FP32 kernel sums in two levels: one
+// float32 accumulator over all S terms has a rounding error growing like
+// 2^-24 sqrt(S / 2), about 3.4e-6 at 16384 samples (the maps' 1e-5 bound).
+constexpr int64_t kNyqPlainSumMax = 16384;
+
 struct NyqArgs {
   const double* cand;      // [3][J]
   const double* mic;       // [M][3]
@@ -130,12 +135,9 @@ __device__ __forceinline__ void nyq_run(const NyqArgs& a, const double* __restri
         x = ((pm[0] - pn[0]) * st.qx[ct] + (pm[1] - pn[1]) * st.qy[ct] +
              (pm[2] - pn[2]) * st.qz[ct]) * a.inv_cT;
       } else {
-        if (new_m) {
-          const double ax = st.qx[ct] - pm[0], ay = st.qy[ct] - pm[1], az = st.qz[ct] - pm[2];
-          st.rm[ct] = sqrt(ax * ax + ay * ay + az * az);
-        }
-        const double bx = st.qx[ct] - pn[0], by = st.qy[ct] - pn[1], bz = st.qz[ct] - pn[2];
-        x = (st.rm[ct] - sqrt(bx * bx + by * by + bz * bz)) * a.inv_cT;
+        if (new_m) st.rm[ct] = norm3(st.qx[ct] - pm[0], st.qy[ct] - pm[1], st.qz[ct] - pm[2]);
+        x = (st.rm[ct] - norm3(st.qx[ct] - pn[0], st.qy[ct] - pn[1], st.qz[ct] - pn[2])) *
+            a.inv_cT;
       }
       const double r = rint(x);
       double f = x - r;
@@ -203,7 +205,11 @@ __device__ __forceinline__ void nyq_run(const NyqArgs& a, const double* __restri
   if (s < steps) contract(av0, w0);
 }
 
-template <int CT, int FT>
+// COMP: two-level summation for long sample sets. The matrix-core
+// accumulator then holds one pair's contribution and is added into a second
+// float32 accumulator whenever the pair changes, so rounding grows with the
+// number of pairs and the steps per pair instead of with S.
+template <int CT, int FT, bool COMP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void nyquist_f32_kernel(NyqArgs a, const double* __restrict__ mic,
                         const PairDesc* __restrict__ pairs, const LagRun* __restrict__ runs) {
@@ -243,12 +249,33 @@ void nyquist_f32_kernel(NyqArgs a, const double* __restrict__ mic,
   for (int i = tid; i < FB; i += 256) kbest[i] = 0ull;
 
   floatx16 acc[CT][FT];
+  floatx16 hi[COMP ? CT : 1][COMP ? FT : 1];
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
     for (int ft = 0; ft < FT; ++ft)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[ct][ft][r] = 0.0f;
+  if (COMP) {
+#pragma unroll
+    for (int ct = 0; ct < (COMP ? CT : 1); ++ct)
+#pragma unroll
+      for (int ft = 0; ft < (COMP ? FT : 1); ++ft)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) hi[ct][ft][r] = 0.0f;
+  }
+  auto fold = [&](int p) {
+    if (COMP && p != st.cur_p && st.cur_p >= 0) {
+#pragma unroll
+      for (int ct = 0; ct < (COMP ? CT : 1); ++ct)
+#pragma unroll
+        for (int ft = 0; ft < (COMP ? FT : 1); ++ft) {
+          hi[ct][ft] += acc[ct][ft];
+#pragma unroll
+          for (int r = 0; r < 16; ++r) acc[ct][ft][r] = 0.0f;
+        }
+    }
+  };
 
   {
     const LagRun r0 = runs[0];
@@ -264,6 +291,7 @@ void nyquist_f32_kernel(NyqArgs a, const double* __restrict__ mic,
       const LagRun nx = runs[ri + 1];
       const int nx_off = pairs[nx.p].off;
       stage_run(a, nx, nx_off, xs1, f0, nrows, wave, lane);
+      fold(run.p);
       nyq_run<CT, FT>(a, mic, run, pd, st, xs0, cl, g, acc);
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
@@ -275,10 +303,18 @@ void nyquist_f32_kernel(NyqArgs a, const double* __restrict__ mic,
         const LagRun nx = runs[ri + 2];
         stage_run(a, nx, pairs[nx.p].off, xs0, f0, nrows, wave, lane);
       }
+      fold(run.p);
       nyq_run<CT, FT>(a, mic, run, pd, st, xs1, cl, g, acc);
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
     }
+  }
+
+  if (COMP) {
+#pragma unroll
+    for (int ct = 0; ct < (COMP ? CT : 1); ++ct)
+#pragma unroll
+      for (int ft = 0; ft < (COMP ? FT : 1); ++ft) acc[ct][ft] += hi[ct][ft];
   }
 
   // epilogue: D[frame][cand], lane (cl, g), register r -> frame 8 (r / 4) + 4 g + r % 4
@@ -298,6 +334,220 @@ void nyquist_f32_kernel(NyqArgs a, const double* __restrict__ mic,
           const unsigned long long k = peak_key(v, static_cast<unsigned>(ci));
           best = k > best ? k : best;
         }
+      }
+      if (a.keys) {
+        best = half_wave_max(best);
+        if (cl == 0 && best) atomicMax(&kbest[fl], best);
+      }
+    }
+  }
+  if (a.keys) {
+    __syncthreads();
+    for (int i = tid; i < FB; i += 256) {
+      const unsigned long long k = kbest[i];
+      if (k && f0 + i < a.F) atomicMax(a.keys + 2 * (size_t)(f0 + i), k);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// BF16 / FP16 kernel (v_mfma_f32_32x32x16_{bf16,f16}, float32 accumulation).
+// One step consumes 16 lags: lane (cl, g) holds 8 consecutive lags 8g .. 8g+7
+// of the step, for frame cl (A = samples from LDS) and candidate cl (B =
+// weights). Each wave owns 32 candidates and all 32 * FT frames of the block,
+// so every weight is reused FT times. Weights come in pairs from one
+// reciprocal: with r = 1 / (d_j d_{j+1}),  1/d_j = d_{j+1} r  and
+// 1/d_{j+1} = d_j r. The samples are copied to LDS in 16-byte chunks (the
+// sample layout aligns each pair window to 8 samples); chunk c of row r is
+// stored at chunk c ^ (r & 7), so the 8 rows that one 128-byte LDS cycle
+// serves hit 8 different chunks.
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+
+template <typename T> struct MxVec;
+template <> struct MxVec<__bf16> {
+  typedef bf16x8 type;
+  static __device__ __forceinline__ floatx16 mfma(bf16x8 a, bf16x8 b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct MxVec<_Float16> {
+  typedef halfx8 type;
+  static __device__ __forceinline__ floatx16 mfma(halfx8 a, halfx8 b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+constexpr int kRowH = kNyqRunMax;  // elements per LDS row (64 lags, 128 bytes)
+
+// Copies one lag run into the swizzled tile [FB][64]: each instruction moves
+// 8 rows (64 lanes x 16 bytes); wave w handles rows 8w, 8w + 32, ...
+template <typename T, int FB>
+__device__ __forceinline__ void stage_run_mx(const T* __restrict__ xi, int S, int F, int f0,
+                                             int nrows, const LagRun& run, int off, T* tile,
+                                             int wave, int lane) {
+  typedef __attribute__((address_space(3))) void* lds_ptr;
+  if (run.len <= 0) return;
+  const int nch = (run.len + 7) >> 3;            // 16-byte chunks holding the run
+  const int rsub = lane >> 3;                    // row within the 8-row group
+  const int cp = lane & 7;                       // physical chunk in LDS
+  for (int rb = 8 * wave; rb < nrows; rb += 32) {
+    const int row = rb + rsub;
+    const int c = cp ^ (row & 7);                // logical chunk stored at cp
+    const int cc = c < nch ? c : nch - 1;
+    const int rr = row < nrows ? row : nrows - 1;
+    const T* src = xi + (size_t)(f0 + rr) * S + off + run.t0 + 8 * cc;
+    __builtin_amdgcn_global_load_lds(src, (lds_ptr)(tile + rb * kRowH), 16, 0, 0);
+  }
+}
+
+template <typename T, int FT>
+__device__ __forceinline__ void nyq_run_mx(const NyqArgs& a, const double* __restrict__ mic,
+                                           const LagRun& run, const PairDesc& pd,
+                                           LaneState<1>& st, const T* tile, int cl, int g,
+                                           floatx16 (&acc)[FT]) {
+  typedef typename MxVec<T>::type vec8;
+  if (run.len <= 0) return;
+  if (run.p != st.cur_p) {
+    st.cur_p = run.p;
+    const double* pm = mic + 3 * pd.m;
+    const double* pn = mic + 3 * pd.mp;
+    const bool new_m = pd.m != st.cur_m;
+    st.cur_m = pd.m;
+    double x;
+    if (a.far_field) {
+      x = ((pm[0] - pn[0]) * st.qx[0] + (pm[1] - pn[1]) * st.qy[0] +
+           (pm[2] - pn[2]) * st.qz[0]) * a.inv_cT;
+    } else {
+      if (new_m) st.rm[0] = norm3(st.qx[0] - pm[0], st.qy[0] - pm[1], st.qz[0] - pm[2]);
+      x = (st.rm[0] - norm3(st.qx[0] - pn[0], st.qy[0] - pn[1], st.qz[0] - pn[2])) * a.inv_cT;
+    }
+    const double r = rint(x);
+    double f = x - r;
+    f = fabs(f) < 1e-30 ? 1e-30 : f;
+    st.xr[0] = static_cast<int>(r);
+    st.xf[0] = static_cast<float>(f);
+    st.sp[0] = sinpi_over_pi(f);
+  }
+  // lane's first lag of step 0: n = -h + t0 + 8g;  d_j = (ia - 16 s - j) + xf,
+  // the integer part formed exactly first so that the only rounding is the
+  // final addition of xf (d_j is then never 0, since xf != 0)
+  const int ia = st.xr[0] + pd.h - run.t0 - 8 * g;
+  const float qs = (ia & 1) ? -st.sp[0] : st.sp[0];
+  const float xf = st.xf[0];
+  float base = static_cast<float>(ia);
+  const int steps = (run.len + 15) >> 4;
+  const int rowsw = cl & 7;
+  for (int s = 0; s < steps; ++s, base -= 16.0f) {
+    vec8 av[FT];
+    const int pc = (2 * s + g) ^ rowsw;
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft)
+      av[ft] = *reinterpret_cast<const vec8*>(tile + (ft * 32 + cl) * kRowH + 8 * pc);
+    float w[8];
+#pragma unroll
+    for (int j = 0; j < 8; j += 2) {
+      const float d0 = (base - static_cast<float>(j)) + xf;
+      const float d1 = (base - static_cast<float>(j + 1)) + xf;
+      const float qr = qs * __builtin_amdgcn_rcpf(d0 * d1);
+      w[j] = qr * d1;
+      w[j + 1] = -qr * d0;
+    }
+    if (16 * s + 16 > run.len) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) w[j] = 16 * s + 8 * g + j < run.len ? w[j] : 0.0f;
+    }
+    vec8 wv;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) wv[j] = static_cast<T>(w[j]);
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft) acc[ft] = MxVec<T>::mfma(av[ft], wv, acc[ft]);
+  }
+}
+
+template <typename T, int FT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void nyquist_mx_kernel(NyqArgs a, const T* __restrict__ xi, const double* __restrict__ mic,
+                       const PairDesc* __restrict__ pairs, const LagRun* __restrict__ runs) {
+  constexpr int FB = 32 * FT;
+  constexpr int JB = 4 * 32;
+  __shared__ __attribute__((aligned(16))) T xs0[FB * kRowH];
+  __shared__ __attribute__((aligned(16))) T xs1[FB * kRowH];
+  __shared__ unsigned long long kbest[FB];
+
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid & 63;
+  const int cl = lane & 31;
+  const int g = lane >> 5;
+  const int64_t jb = (int64_t)blockIdx.x * JB + wave * 32;
+  const int f0 = blockIdx.y * FB;
+  const int nrows = a.F - f0 < FB ? a.F - f0 : FB;
+
+  LaneState<1> st;
+  {
+    int64_t ci = jb + cl;
+    ci = ci < a.J ? ci : a.J - 1;
+    st.qx[0] = a.cand[ci];
+    st.qy[0] = a.cand[a.J + ci];
+    st.qz[0] = a.cand[2 * a.J + ci];
+    st.rm[0] = 0.0;
+    st.xr[0] = 0;
+    st.xf[0] = 0.0f;
+    st.sp[0] = 0.0f;
+  }
+  st.cur_m = -1;
+  st.cur_p = -1;
+  for (int i = tid; i < FB; i += 256) kbest[i] = 0ull;
+
+  floatx16 acc[FT];
+#pragma unroll
+  for (int ft = 0; ft < FT; ++ft)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[ft][r] = 0.0f;
+
+  {
+    const LagRun r0 = runs[0];
+    stage_run_mx<T, FB>(xi, a.S, a.F, f0, nrows, r0, pairs[r0.p].off, xs0, wave, lane);
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  for (int ri = 0; ri < a.n_runs; ri += 2) {
+    {
+      const LagRun run = runs[ri];
+      const PairDesc pd = pairs[run.p];
+      const LagRun nx = runs[ri + 1];
+      stage_run_mx<T, FB>(xi, a.S, a.F, f0, nrows, nx, pairs[nx.p].off, xs1, wave, lane);
+      nyq_run_mx<T, FT>(a, mic, run, pd, st, xs0, cl, g, acc);
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+    }
+    {
+      const LagRun run = runs[ri + 1];
+      const PairDesc pd = pairs[run.p];
+      if (ri + 2 < a.n_runs) {
+        const LagRun nx = runs[ri + 2];
+        stage_run_mx<T, FB>(xi, a.S, a.F, f0, nrows, nx, pairs[nx.p].off, xs0, wave, lane);
+      }
+      nyq_run_mx<T, FT>(a, mic, run, pd, st, xs1, cl, g, acc);
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+    }
+  }
+
+  const int64_t ci = jb + cl;
+#pragma unroll
+  for (int ft = 0; ft < FT; ++ft) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int fl = ft * 32 + 8 * (r >> 2) + 4 * g + (r & 3);
+      const int fg = f0 + fl;
+      unsigned long long best = 0ull;
+      const float v = 2.0f * acc[ft][r];
+      if (ci < a.J && fg < a.F) {
+        if (a.map) a.map[(size_t)fg * a.J + ci] = v;
+        best = peak_key(v, static_cast<unsigned>(ci));
       }
       if (a.keys) {
         best = half_wave_max(best);
@@ -380,7 +630,7 @@ __global__ __launch_bounds__(256) void nyquist_f64_kernel(NyqArgs a) {
 
 }  // namespace
 
-hipError_t launch_nyquist(const srp_geometry_s* g, const float* xi, int F, int dtype, float* map,
+hipError_t launch_nyquist(const srp_geometry_s* g, const void* xi, int F, int dtype, float* map,
                           unsigned long long* keys, hipStream_t s) {
   NyqArgs a;
   a.cand = g->d_cand;
@@ -388,7 +638,7 @@ hipError_t launch_nyquist(const srp_geometry_s* g, const float* xi, int F, int d
   a.pairs = g->d_pairs;
   a.runs = g->d_nyq_runs;
   a.n_runs = static_cast<int>(g->nyq_runs.size());
-  a.xi = xi;
+  a.xi = static_cast<const float*>(xi);
   a.F = F;
   a.S = static_cast<int>(g->info.S);
   a.J = g->info.J;
@@ -397,11 +647,32 @@ hipError_t launch_nyquist(const srp_geometry_s* g, const float* xi, int F, int d
   a.map = map;
   a.keys = keys;
   if (dtype == SRP_FP32) {
-    constexpr int CT = 2, FT = 4;
-    constexpr int JB = 4 * 32 * CT, FB = 32 * FT;
+    constexpr int FT = 4, FB = 32 * FT;
+    int64_t samples = 0;
+    for (const PairDesc& pd : g->pairs) samples += 2 * pd.h + 1;
+    if (samples <= kNyqPlainSumMax) {
+      constexpr int CT = 2, JB = 4 * 32 * CT;
+      dim3 grid(static_cast<unsigned>((a.J + JB - 1) / JB), (F + FB - 1) / FB);
+      hipLaunchKernelGGL((nyquist_f32_kernel<CT, FT, false>), grid, dim3(256), 0, s, a, a.mic,
+                         a.pairs, a.runs);
+    } else {
+      constexpr int CT = 1, JB = 4 * 32 * CT;
+      dim3 grid(static_cast<unsigned>((a.J + JB - 1) / JB), (F + FB - 1) / FB);
+      hipLaunchKernelGGL((nyquist_f32_kernel<CT, FT, true>), grid, dim3(256), 0, s, a, a.mic,
+                         a.pairs, a.runs);
+    }
+    return hipGetLastError();
+  }
+  if (dtype == SRP_BF16 || dtype == SRP_FP16) {
+    constexpr int FT = 8;
+    constexpr int JB = 4 * 32, FB = 32 * FT;
     dim3 grid(static_cast<unsigned>((a.J + JB - 1) / JB), (F + FB - 1) / FB);
-    hipLaunchKernelGGL((nyquist_f32_kernel<CT, FT>), grid, dim3(256), 0, s, a, a.mic, a.pairs,
-                       a.runs);
+    if (dtype == SRP_BF16)
+      hipLaunchKernelGGL((nyquist_mx_kernel<__bf16, FT>), grid, dim3(256), 0, s, a,
+                         static_cast<const __bf16*>(xi), a.mic, a.pairs, a.runs);
+    else
+      hipLaunchKernelGGL((nyquist_mx_kernel<_Float16, FT>), grid, dim3(256), 0, s, a,
+                         static_cast<const _Float16*>(xi), a.mic, a.pairs, a.runs);
     return hipGetLastError();
   }
   if (dtype == SRP_FP64) {

@@ -53,7 +53,9 @@ double dist3(const double* a, const double* b) {
   return std::sqrt(dx * dx + dy * dy + dz * dz);
 }
 
-// Per-pair window half-widths (Section 3.2): N_p = floor(d_p / (c T)).
+// Per-pair window half-widths (Section 3.2): N_p = floor(d_p / (c T)), and
+// the sample layout: pair p's W_p = 2 (N_p + N_aux) + 1 samples start at
+// offsets[p], a multiple of kSampleAlign.
 srp_status layout(const double* mic, int M, double c, double f_max, int n_aux,
                   std::vector<int32_t>& N_p, std::vector<int64_t>& offsets) {
   if (mic == nullptr) return fail(SRP_ERR_INVALID_ARG, "mic_xyz is NULL");
@@ -75,7 +77,9 @@ srp_status layout(const double* mic, int M, double c, double f_max, int n_aux,
       const double q = std::floor(d / (c * T));
       if (q > 1.0e8) return fail(SRP_ERR_INVALID_ARG, "pair window too long");
       N_p[p] = static_cast<int32_t>(q);
-      offsets[p + 1] = offsets[p] + 2 * (int64_t)(N_p[p] + n_aux) + 1;
+      // windows start at multiples of kSampleAlign samples (zero-filled gaps)
+      const int64_t W = 2 * (int64_t)(N_p[p] + n_aux) + 1;
+      offsets[p + 1] = offsets[p] + (W + kSampleAlign - 1) / kSampleAlign * kSampleAlign;
     }
   }
   return SRP_OK;
@@ -323,14 +327,15 @@ srp_status srp_cross_spectra(const srp_geometry_t* g, const float* frames, int32
 }
 
 srp_status srp_gcc_samples(const srp_geometry_t* g, const float* psi, int32_t F, int32_t dtype,
-                           float* xi, void* stream) {
+                           void* xi, void* stream) {
   if (g == nullptr || psi == nullptr || xi == nullptr)
     return fail(SRP_ERR_INVALID_ARG, "srp_gcc_samples: NULL argument");
   if (F < 1) return fail(SRP_ERR_INVALID_ARG, "F must be >= 1");
-  if (dtype != SRP_FP32) return fail(SRP_ERR_UNSUPPORTED, "srp_gcc_samples computes in FP32");
+  if (dtype != SRP_FP32 && dtype != SRP_BF16 && dtype != SRP_FP16)
+    return fail(SRP_ERR_UNSUPPORTED, "srp_gcc_samples stores FP32, BF16 or FP16");
   DeviceGuard dg(g->device);
   if (!dg.ok) return fail(SRP_ERR_DEVICE, "cannot select the geometry's device");
-  hipError_t e = launch_gcc_samples(g, reinterpret_cast<const float2*>(psi), F, xi,
+  hipError_t e = launch_gcc_samples(g, reinterpret_cast<const float2*>(psi), F, dtype, xi,
                                     static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return device_fail(e, "gcc_samples");
   return SRP_OK;
@@ -347,7 +352,7 @@ static srp_status check_map_args(const srp_geometry_t* g, const void* in, int32_
   return SRP_OK;
 }
 
-srp_status srp_map_nyquist(const srp_geometry_t* g, const float* xi, int32_t F, int32_t dtype,
+srp_status srp_map_nyquist(const srp_geometry_t* g, const void* xi, int32_t F, int32_t dtype,
                            float* map, srp_peak* peaks, void* stream) {
   srp_status st = check_map_args(g, xi, F, dtype, map, peaks);
   if (st != SRP_OK) return st;

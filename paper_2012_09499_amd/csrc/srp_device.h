@@ -9,6 +9,18 @@ namespace srp {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
+// ||(dx, dy, dz)|| in float64 from the hardware reciprocal square root refined
+// by two Newton steps y <- y (3/2 - s y^2 / 2) (relative error ~1e-16, far
+// below what a TDOA needs); 0 at the origin.
+__device__ __forceinline__ double norm3(double dx, double dy, double dz) {
+  const double s = dx * dx + dy * dy + dz * dz;
+  const double h = 0.5 * s;
+  double y = __builtin_amdgcn_rsq(s);
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return s > 0.0 ? s * y : 0.0;
+}
+
 // Unsigned key whose integer order is the float order of `v` (finite or inf),
 // with the candidate index in the low word so that, among equal values, the
 // LOWEST index has the LARGEST key. Key 0 means "no candidate yet".

@@ -28,6 +28,9 @@ struct LagRun {
 // Lag runs of the Nyquist interpolation kernels are at most this long (one
 // lane per lag when a wave copies a run into LDS).
 constexpr int kNyqRunMax = 64;
+// Pair windows of the GCC-sample layout start at multiples of this many
+// samples (16 bytes of bf16/fp16), so staging copies can move 16-byte chunks.
+constexpr int kSampleAlign = 8;
 // Bin runs of the conventional kernel are at most this many bins.
 constexpr int kConvRunBins = 32;
 // Lag tiles of the GCC-sample kernel are 32 lags wide (one matrix-core tile).
@@ -71,9 +74,9 @@ hipError_t launch_fft_phat(const srp_geometry_s* g, const float* frames, int F, 
                            hipStream_t s);
 hipError_t launch_cross(const srp_geometry_s* g, const float2* ytil, int F, float2* psi,
                         hipStream_t s);
-hipError_t launch_gcc_samples(const srp_geometry_s* g, const float2* psi, int F, float* xi,
-                              hipStream_t s);
-hipError_t launch_nyquist(const srp_geometry_s* g, const float* xi, int F, int dtype, float* map,
+hipError_t launch_gcc_samples(const srp_geometry_s* g, const float2* psi, int F, int dtype,
+                              void* xi, hipStream_t s);
+hipError_t launch_nyquist(const srp_geometry_s* g, const void* xi, int F, int dtype, float* map,
                           unsigned long long* keys, hipStream_t s);
 hipError_t launch_conventional(const srp_geometry_s* g, const float2* psi, int F, int dtype,
                                float* map, unsigned long long* keys, hipStream_t s);

@@ -16,7 +16,9 @@ class SrpPipeline:
         self.F = int(F)
         self.workspace = torch.empty(geom.workspace_bytes(F), dtype=torch.uint8, device=device)
         self.psi = torch.empty((F, geom.P, geom.K), dtype=torch.complex64, device=device)
+        self.device = device
         self.xi = torch.empty((F, geom.S), dtype=torch.float32, device=device)
+        self._xi_lowp = {}
         self.peaks = torch.empty((F, 2), dtype=torch.int64, device=device)
         self.map = (torch.empty((F, geom.J), dtype=torch.float32, device=device)
                     if keep_map else None)
@@ -25,10 +27,20 @@ class SrpPipeline:
         return S.cross_spectra(self.g, frames, out=self.psi[:frames.shape[0]],
                                workspace=self.workspace)
 
+    def samples_buffer(self, dtype: str):
+        import torch
+        if S.sample_torch_dtype(dtype) == torch.float32:
+            return self.xi
+        if dtype not in self._xi_lowp:
+            self._xi_lowp[dtype] = torch.empty((self.F, self.g.S),
+                                               dtype=S.sample_torch_dtype(dtype),
+                                               device=self.device)
+        return self._xi_lowp[dtype]
+
     def nyquist(self, frames, dtype: str = "fp32"):
         F = frames.shape[0]
         psi = self.spectra(frames)
-        xi = S.gcc_samples(self.g, psi, out=self.xi[:F])
+        xi = S.gcc_samples(self.g, psi, out=self.samples_buffer(dtype)[:F], dtype=dtype)
         return S.map_nyquist(self.g, xi, dtype=dtype, want_map=self.map is not None,
                              map_out=None if self.map is None else self.map[:F],
                              peaks_out=self.peaks[:F])

@@ -46,15 +46,19 @@ def test_pair_layout_matches_oracle(seed):
     N_p, off, Sx = S.pair_layout(mic, 343.0, f_max, n_aux)
     win = O.pair_windows(mic, 343.0, f_max, n_aux)
     np.testing.assert_array_equal(N_p, win["N"])
-    np.testing.assert_array_equal(off, win["offsets"])
-    assert Sx == win["S"]
+    # library layout: each window starts at a multiple of 8 samples
+    padded = (win["W"] + 7) // 8 * 8
+    np.testing.assert_array_equal(off, np.concatenate([[0], np.cumsum(padded)]))
+    assert np.all(off % 8 == 0) and np.all(np.diff(off) >= win["W"])
+    assert Sx == off[-1]
 
 
 def test_pair_layout_paper_array():
     mic = WL.uniform_circular_array(6, 0.1)
     N_p, off, Sx = S.pair_layout(mic, 340.0, 8000.0, 2)
     assert sorted(N_p.tolist()) == [4] * 6 + [8] * 6 + [9] * 3
-    assert Sx == 2 * 99 + 15 * 5
+    # windows of 13, 21 and 23 samples, each padded to a multiple of 8
+    assert Sx == 6 * 16 + 6 * 24 + 3 * 24
 
 
 def _geometry_status(**kw):

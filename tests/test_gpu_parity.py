@@ -3,6 +3,10 @@
 Tolerances (written here, derived in the design doc):
 * FP32 maps: relative L2 error per frame <= 1e-5; argmax identical in >= 99 %
   of frames, any other frame a near-tie within the map tolerance.
+* BF16 / FP16 maps (weights and samples in that type, float32 accumulation):
+  relative L2 error per frame <= 1e-2 against the FP64 oracle run from the
+  frames; argmax as above with that tolerance.
+* BF16 / FP16 GCC samples: exactly the float32 samples rounded to that type.
 * FP64 map instances from the same float32 samples: <= 1e-12.
 * PHAT cross-spectra: relative L2 error per frame <= 1e-5 (float32 FFT).
 * GCC samples from the same psi: relative L2 error per frame <= 1e-5 (a
@@ -24,6 +28,7 @@ torch = pytest.importorskip("torch")
 import paper_2012_09499_amd as srp  # noqa: E402
 
 MAP_TOL = 1e-5
+LOWP_TOL = 1e-2
 PSI_TOL = 1e-5
 XI_TOL = 1e-5
 
@@ -66,6 +71,9 @@ CASES = {
                                               L=4096, F=2, seed=5, box=(1.2, 1.0, 0.6)),
     "m6_L1024_fmax4k_F4": lambda: WL.make_custom(M=6, J_shape=(7, 6, 5), L=1024, F=4, seed=6,
                                                  f_max=4000.0),
+    # S ~ 40k samples and 2KP ~ 280k terms: the two-level-sum kernel variants
+    "m24_L1024_48k_F3": lambda: WL.make_custom(M=24, J_shape=(9, 7, 5), h=0.15, fs=48000.0,
+                                               L=1024, F=3, seed=9, box=(1.0, 1.0, 0.6)),
 }
 
 
@@ -95,7 +103,13 @@ def test_gcc_samples(cases, name):
     xi = srp.gcc_samples(g, psi)
     torch.cuda.synchronize()
     ref = R.oracle_xi(wl, _c128(psi))
-    got = xi.cpu().numpy().astype(np.float64)
+    got = srp.unpack_samples(g, xi)
+    # the layout's alignment gaps after each window are zeros
+    full = xi.cpu().numpy()
+    gaps = np.ones(g.S, dtype=bool)
+    for o, w in zip(g.offsets[:-1], g.W):
+        gaps[o:o + w] = False
+    assert np.all(full[:, gaps] == 0.0) and np.all(g.offsets % 8 == 0)
     assert _rel(got, ref).max() <= XI_TOL
     # elementwise: a float32 sum of 2K terms whose magnitudes add up to at most
     # sum_k w_k <= L; the worst-case rounding bound 2K u L (u = 2^-24) exceeds
@@ -112,7 +126,7 @@ def test_nyquist_map_from_same_samples(cases, name, dtype):
     xi = srp.gcc_samples(g, psi)
     m, pk = srp.map_nyquist(g, xi, dtype=dtype)
     torch.cuda.synchronize()
-    ref = R.oracle_nyquist(wl, xi.cpu().numpy().astype(np.float64), wl.candidates())
+    ref = R.oracle_nyquist(wl, srp.unpack_samples(g, xi), wl.candidates())
     got = m.cpu().numpy().astype(np.float64)
     tol = MAP_TOL if dtype == "fp32" else 1e-12
     # the fp64 kernel writes a float32 map: compare at float32 resolution
@@ -281,3 +295,62 @@ def test_config1_full():
     refc = R.oracle_conventional(wl, psi_ref, wl.candidates())
     assert _rel(m.cpu().numpy(), refc).max() <= MAP_TOL
     R.check_argmax(srp.decode_peaks(pk)[0], refc, MAP_TOL)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("dtype", ["bf16", "fp16"])
+def test_lowp_samples_are_rounded_fp32_samples(cases, name, dtype):
+    wl = cases[name]
+    g = _geom(wl)
+    psi = srp.cross_spectra(g, _frames(wl))
+    x32 = srp.gcc_samples(g, psi)
+    xlo = srp.gcc_samples(g, psi, dtype=dtype)
+    torch.cuda.synchronize()
+    assert xlo.dtype == srp.sample_torch_dtype(dtype)
+    assert torch.equal(x32.to(xlo.dtype), xlo)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("dtype", ["bf16", "fp16"])
+def test_nyquist_lowp_pipeline(cases, name, dtype):
+    """Frames -> BF16/FP16 Nyquist map against the FP64 oracle run from the frames."""
+    wl = cases[name]
+    g = _geom(wl)
+    pipe = srp.SrpPipeline(g, wl.F, keep_map=True)
+    m, pk = pipe.nyquist(_frames(wl), dtype=dtype)
+    torch.cuda.synchronize()
+    psi_ref = R.oracle_psi(wl)
+    ref = R.oracle_nyquist(wl, R.oracle_xi(wl, psi_ref), wl.candidates())
+    got = m.cpu().numpy().astype(np.float64)
+    err = _rel(got, ref)
+    assert err.max() <= LOWP_TOL, err
+    idx = srp.decode_peaks(pk)[0]
+    np.testing.assert_array_equal(idx, np.argmax(got, axis=1))
+    R.check_argmax(idx, ref, LOWP_TOL)
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "bf16", "fp16"])
+def test_near_integer_tdoa_stays_finite(dtype):
+    """TDOAs within 1e-10 .. 1e-7 samples of an integer (|x - rint(x)| tiny but not 0).
+
+    Regression: a weight denominator formed as base + (xf - j) lost xf and hit
+    exactly 0 there, giving NaN maps.
+    """
+    fs, c, L = 16000.0, 343.0, 256
+    d = 10 * c / fs
+    mic = np.array([[0.0, 0.0, 0.0], [d, 0.0, 0.0]])
+    xs = [k + e for k in (-7, -3, 0, 1, 3, 7) for e in (1e-10, -1e-10, 3e-8, -1e-7)]
+    a = (d - np.asarray(xs) * c / fs) / 2.0  # on the axis between the mics: x = (d - 2a) fs / c
+    cand = np.stack([a, np.zeros_like(a), np.zeros_like(a)], axis=1)
+    rng = np.random.default_rng(5)
+    y = rng.standard_normal((3, 2, L)).astype(np.float32)
+    g = srp.Geometry(mic, cand, fs=fs, L=L, c=c, n_aux=2)
+    pipe = srp.SrpPipeline(g, 3, keep_map=True)
+    m, _ = pipe.nyquist(torch.from_numpy(y).cuda(), dtype=dtype)
+    torch.cuda.synchronize()
+    got = m.cpu().numpy().astype(np.float64)
+    assert np.all(np.isfinite(got))
+    wl = WL.Workload(name="nearint", mic_xyz=mic, grid=None, fs=fs, L=L, F=3, c=c, n_aux=2,
+                     frames=y)
+    ref = R.oracle_nyquist(wl, R.oracle_xi(wl, R.oracle_psi(wl)), cand)
+    assert _rel(got, ref).max() <= (MAP_TOL if dtype == "fp32" else LOWP_TOL)
