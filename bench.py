@@ -85,6 +85,63 @@ def cpu_baseline(wl, n_cand: int, seed: int = 0):
     return info, idx, ref
 
 
+def serving_run(seconds: float, rate_per_array: float = 31.25, seed: int = 4):
+    """The serving workload: 64 arrays (M in {4, 8, 16, 32}, J log-uniform in
+    [1e4, 2e6]), Poisson frame arrivals, continuous batching (FP32)."""
+    import torch
+    import workloads as WL
+    from paper_2012_09499_amd import serving as SV
+
+    arrays = WL.serving_arrays(64, seed=seed)
+    fs, L, c = 16000.0, 1024, 343.0
+    rng = np.random.default_rng(seed)
+    srv = SV.SrpServer()
+    frames = {}
+    t_setup = time.perf_counter()
+    for a in arrays:
+        srv.open_array(a["id"], a["mic_xyz"], a["grid"].points(), fs=fs, L=L, c=c, n_aux=2)
+        r1, r2 = np.random.default_rng(rng.integers(1 << 31)), np.random.default_rng(
+            rng.integers(1 << 31))
+        fr = WL.synth_frames(a["mic_xyz"], a["source"], fs, L, 4, c, 10.0, r1, r2)
+        frames[a["id"]] = fr
+    t_setup = time.perf_counter() - t_setup
+    # warm-up: one frame per array
+    for a in arrays:
+        srv.submit(a["id"], frames[a["id"]][0])
+    srv.drain()
+    srv.completed.clear()
+    srv.batch_frames.clear()
+    srv.batches = 0
+    arrivals = []
+    for a in arrays:
+        t = 0.0
+        while True:
+            t += rng.exponential(1.0 / rate_per_array)
+            if t >= seconds:
+                break
+            arrivals.append((t, a["id"]))
+    arrivals.sort()
+    t0 = time.perf_counter()
+    k = 0
+    while k < len(arrivals):
+        now = time.perf_counter() - t0
+        while k < len(arrivals) and arrivals[k][0] <= now:
+            t, i = arrivals[k]
+            srv.submit(i, frames[i][k % 4], t_arrival=t0 + t)
+            k += 1
+        srv.pump()
+    srv.drain()
+    span = time.perf_counter() - t0
+    st = srv.stats(span)
+    Js = [a["grid"].J for a in arrays]
+    Ms = [len(a["mic_xyz"]) for a in arrays]
+    st.update({"offered_frames_per_s": len(arrivals) / seconds, "seconds": seconds,
+               "wall_seconds": span, "arrays": len(arrays), "dtype": "f32",
+               "J_range": [int(min(Js)), int(max(Js))], "mic_counts": sorted(set(Ms)),
+               "setup_seconds": t_setup})
+    return st
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +152,8 @@ def main():
     ap.add_argument("--no-conventional", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-candidates", type=int, default=40000)
+    ap.add_argument("--serving-seconds", type=float, default=10.0,
+                    help="length of the serving run (0 skips it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -244,6 +303,13 @@ def main():
         print(f"[bench] cpu baseline {cb['value']:.3e} evals/s on {cb['cores']} BLAS threads "
               f"({cb['seconds']:.1f}s); sampled map rel err max {err.max():.2e}",
               file=sys.stderr, flush=True)
+
+    if args.serving_seconds > 0:
+        st = serving_run(args.serving_seconds)
+        out["serving"] = st
+        print(f"[bench] serving: {st['frames_per_s']:.0f} frames/s done of "
+              f"{st['offered_frames_per_s']:.0f} offered, p50 {st['latency_ms_p50']:.1f} ms, "
+              f"p99 {st['latency_ms_p99']:.1f} ms", file=sys.stderr, flush=True)
 
     print(json.dumps(out), flush=True)
 

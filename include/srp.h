@@ -175,6 +175,37 @@ srp_status srp_map_conventional(const srp_geometry_t* g, const float* psi, int32
 srp_status srp_map_nyquist(const srp_geometry_t* g, const void* xi, int32_t F, int32_t dtype,
                            float* map, srp_peak* peaks, void* stream);
 
+/* One item of a batched Nyquist launch: an array and its frames of the batch. */
+typedef struct {
+  const srp_geometry_t* g;   /* the array                                            */
+  int64_t xi_offset;         /* index (in floats) of the item's first sample in xi;  */
+                             /* the item's samples are F x S (srp_gcc_samples layout) */
+  int32_t F;                 /* frames of the item, 1 <= F <= 8                      */
+  int32_t reserved;
+  float* map;                /* device F x J float32, written; may be NULL if peaks is not */
+  srp_peak* peaks;           /* device F, written; may be NULL if map is not         */
+} srp_batch_item;
+
+/* Bytes of device workspace srp_map_nyquist_batched needs for n_items items. */
+srp_status srp_map_nyquist_batched_workspace(int32_t n_items, size_t* bytes);
+
+/* Nyquist maps of many arrays in one ragged launch (Eq. SRPapprox summed over
+ * pairs, Eq. SRP_T_IFT), for serving: arrays of different microphone counts,
+ * windows and grids, each with a few frames. Same result definition and
+ * accuracy as srp_map_nyquist; computed on the vector units in float32 (with
+ * one to eight frames per array the weights are formed once per candidate
+ * and lag and used by those frames only).
+ *   items      host, n_items entries (read before the call returns)
+ *   xi         device float32 sample arena holding every item's samples
+ *   dtype      SRP_FP32
+ *   workspace  device, >= srp_map_nyquist_batched_workspace bytes; holds the
+ *              item table until the launch has finished (do not reuse it for
+ *              another batch on another stream before then)
+ * All items must live on one device. */
+srp_status srp_map_nyquist_batched(const srp_batch_item* items, int32_t n_items, const float* xi,
+                                   int32_t dtype, void* workspace, size_t workspace_bytes,
+                                   void* stream);
+
 /* Per-frame argmax of a map (Section 2.2), lowest index on ties.
  *   map    device, F x J float32;  peaks device, F srp_peak, written.
  * F >= 1, 1 <= J < 2^31. */

@@ -6,6 +6,7 @@ include/srp.h); this package is its thin Python binding plus a frame
 pipeline helper.
 """
 from ._lib import (DTYPES, EXPORTS, Geometry, SrpError, argmax, cross_spectra, decode_peaks,  # noqa: F401
-                   gcc_samples, lib, map_conventional, map_nyquist, pair_layout,
-                   sample_torch_dtype, unpack_samples, version)
+                   batched_workspace_bytes, gcc_samples, lib, map_conventional, map_nyquist,
+                   map_nyquist_batched, pair_layout, sample_torch_dtype, unpack_samples,
+                   version)
 from .pipeline import SrpPipeline  # noqa: F401

@@ -31,8 +31,9 @@ PHAT = 0
 # exported symbols of include/srp.h
 EXPORTS = ("srp_pair_layout", "srp_geometry", "srp_geometry_query", "srp_geometry_destroy",
            "srp_cross_spectra_workspace", "srp_cross_spectra", "srp_gcc_samples",
-           "srp_map_conventional", "srp_map_nyquist", "srp_argmax", "srp_last_error",
-           "srp_version")
+           "srp_map_conventional", "srp_map_nyquist", "srp_map_nyquist_batched_workspace",
+           "srp_map_nyquist_batched", "srp_argmax", "srp_last_error", "srp_version")
+BATCH_MAX_F = 8
 
 
 class SrpError(RuntimeError):
@@ -46,6 +47,11 @@ class GeometryInfo(C.Structure):
                 ("J", C.c_int64), ("S", C.c_int64), ("h_max", C.c_int32), ("n_aux", C.c_int32),
                 ("field", C.c_int32), ("window", C.c_int32), ("c", C.c_double),
                 ("fs", C.c_double), ("f_max", C.c_double), ("T", C.c_double)]
+
+
+class BatchItem(C.Structure):
+    _fields_ = [("g", C.c_void_p), ("xi_offset", C.c_int64), ("F", C.c_int32),
+                ("reserved", C.c_int32), ("map", C.c_void_p), ("peaks", C.c_void_p)]
 
 
 _lib = None
@@ -73,6 +79,8 @@ def lib() -> C.CDLL:
     L.srp_map_conventional.argtypes = [vp, vp, i32, i32, vp, vp, vp]
     L.srp_map_nyquist.argtypes = [vp, vp, i32, i32, vp, vp, vp]
     L.srp_argmax.argtypes = [vp, i32, i64, vp, vp]
+    L.srp_map_nyquist_batched_workspace.argtypes = [i32, C.POINTER(C.c_size_t)]
+    L.srp_map_nyquist_batched.argtypes = [vp, i32, vp, i32, vp, C.c_size_t, vp]
     L.srp_last_error.restype = C.c_char_p
     L.srp_last_error.argtypes = []
     L.srp_version.restype = C.c_char_p
@@ -265,6 +273,39 @@ def map_conventional(g: Geometry, psi, dtype: str = "fp32", want_map: bool = Tru
                                       pk.data_ptr() if pk is not None else None,
                                       _stream_handle(stream)))
     return m, pk
+
+
+def batched_workspace_bytes(n_items: int) -> int:
+    n = C.c_size_t(0)
+    _check(lib().srp_map_nyquist_batched_workspace(int(n_items), C.byref(n)))
+    return int(n.value)
+
+
+def map_nyquist_batched(items, xi_arena, workspace, stream=None):
+    """One ragged launch over many arrays (srp_map_nyquist_batched).
+
+    items: list of (Geometry, xi_offset, F, map tensor or None, peaks tensor or None);
+    xi_arena: float32 CUDA tensor holding every item's samples; workspace: CUDA
+    uint8 tensor of at least batched_workspace_bytes(len(items)) bytes.
+    """
+    import torch
+    _need_cuda(xi_arena, "xi_arena", torch.float32)
+    n = len(items)
+    arr = (BatchItem * n)()
+    for i, (g, off, F, m, pk) in enumerate(items):
+        if m is not None:
+            _need_cuda(m, "map", torch.float32, (F, g.J))
+        if pk is not None:
+            _need_cuda(pk, "peaks", torch.int64, (F, 2))
+        arr[i].g = g.handle
+        arr[i].xi_offset = int(off)
+        arr[i].F = int(F)
+        arr[i].map = m.data_ptr() if m is not None else None
+        arr[i].peaks = pk.data_ptr() if pk is not None else None
+    _check(lib().srp_map_nyquist_batched(arr, n, xi_arena.data_ptr(), DTYPES["fp32"],
+                                         workspace.data_ptr(),
+                                         workspace.numel() * workspace.element_size(),
+                                         _stream_handle(stream)))
 
 
 def argmax(srp_map, peaks_out=None, stream=None):

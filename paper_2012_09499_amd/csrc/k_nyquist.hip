@@ -67,23 +67,6 @@ __device__ __forceinline__ double pair_x(const NyqArgs& a, const PairDesc& pd, d
   return (sqrt(ax * ax + ay * ay + az * az) - sqrt(bx * bx + by * by + bz * bz)) * a.inv_cT;
 }
 
-// sin(pi x) / pi for |x| <= 1/2: Taylor series of sin in float64,
-// x * sum_k (-1)^k pi^(2k) x^(2k) / (2k+1)!, truncated after x^17 (relative
-// truncation error < 1e-12 on the interval), then rounded once to float32.
-__device__ __forceinline__ float sinpi_over_pi(double x) {
-  const double u = x * x;
-  double p = 2.531217404137026e-07;  //  pi^16 / 17!
-  p = fma(p, u, -6.975873661656377e-06);  // -pi^14 / 15!
-  p = fma(p, u, 0.00014842879303107092);  //  pi^12 / 13!
-  p = fma(p, u, -0.0023460810354558226);  // -pi^10 / 11!
-  p = fma(p, u, 0.02614784781765479);  //  pi^8 / 9!
-  p = fma(p, u, -0.1907518241220842);  // -pi^6 / 7!
-  p = fma(p, u, 0.8117424252833535);  //  pi^4 / 5!
-  p = fma(p, u, -1.6449340668482264);  // -pi^2 / 3!
-  p = fma(p, u, 1.0);  // 1
-  return static_cast<float>(x * p);
-}
-
 // Issues the asynchronous copy of one lag run of the samples into an LDS
 // tile [frame][lag] (row stride kStride): wave w copies rows w, w + 4, ...
 // below nrows = min(FB, F - f0), one lane per lag. Lanes past the run copy the

@@ -387,6 +387,68 @@ srp_status srp_map_conventional(const srp_geometry_t* g, const float* psi, int32
   return SRP_OK;
 }
 
+srp_status srp_map_nyquist_batched_workspace(int32_t n_items, size_t* bytes) {
+  if (bytes == nullptr || n_items < 1) return fail(SRP_ERR_INVALID_ARG, "n_items must be >= 1");
+  *bytes = (size_t)n_items * sizeof(BatchItemDev);
+  return SRP_OK;
+}
+
+srp_status srp_map_nyquist_batched(const srp_batch_item* items, int32_t n_items, const float* xi,
+                                   int32_t dtype, void* workspace, size_t workspace_bytes,
+                                   void* stream) {
+  if (items == nullptr || xi == nullptr || workspace == nullptr)
+    return fail(SRP_ERR_INVALID_ARG, "srp_map_nyquist_batched: NULL argument");
+  if (n_items < 1) return fail(SRP_ERR_INVALID_ARG, "n_items must be >= 1");
+  if (dtype != SRP_FP32) return fail(SRP_ERR_UNSUPPORTED, "the batched path computes in FP32");
+  if (workspace_bytes < (size_t)n_items * sizeof(BatchItemDev))
+    return fail(SRP_ERR_INVALID_ARG, "workspace too small");
+  std::vector<BatchItemDev> dev(n_items);
+  int64_t blocks = 0;
+  int max_f = 1;
+  int device = -1;
+  for (int i = 0; i < n_items; ++i) {
+    const srp_batch_item& it = items[i];
+    if (it.g == nullptr) return fail(SRP_ERR_INVALID_ARG, "item geometry is NULL");
+    if (it.F < 1 || it.F > kBatchMaxF)
+      return fail(SRP_ERR_INVALID_ARG, "item F must be in [1, 8]");
+    if (it.map == nullptr && it.peaks == nullptr)
+      return fail(SRP_ERR_INVALID_ARG, "item map and peaks are both NULL");
+    if (it.xi_offset < 0) return fail(SRP_ERR_INVALID_ARG, "negative xi_offset");
+    if (device >= 0 && it.g->device != device)
+      return fail(SRP_ERR_INVALID_ARG, "items on different devices");
+    device = it.g->device;
+    BatchItemDev& d = dev[i];
+    d.cand = it.g->d_cand;
+    d.mic = it.g->d_mic;
+    d.pairs = it.g->d_pairs;
+    d.J = it.g->info.J;
+    d.xi_off = it.xi_offset;
+    d.S = static_cast<int>(it.g->info.S);
+    d.P = it.g->info.P;
+    d.F = it.F;
+    d.far_field = it.g->info.field == SRP_FAR_FIELD;
+    d.inv_cT = it.g->inv_cT;
+    d.map = it.map;
+    d.keys = reinterpret_cast<unsigned long long*>(it.peaks);
+    d.block_begin = static_cast<int>(blocks);
+    d.pad = 0;
+    blocks += (d.J + 255) / 256;
+    max_f = it.F > max_f ? it.F : max_f;
+  }
+  if (blocks >= (int64_t(1) << 31)) return fail(SRP_ERR_INVALID_ARG, "batch too large");
+  DeviceGuard dg(device);
+  if (!dg.ok) return fail(SRP_ERR_DEVICE, "cannot select the items' device");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // pageable source: the runtime stages it before returning, so `dev` may go
+  hipError_t e = hipMemcpyAsync(workspace, dev.data(), dev.size() * sizeof(BatchItemDev),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = launch_nyquist_batched(static_cast<const BatchItemDev*>(workspace), n_items,
+                               static_cast<int>(blocks), max_f, xi, s);
+  if (e != hipSuccess) return device_fail(e, "map_nyquist_batched");
+  return SRP_OK;
+}
+
 srp_status srp_argmax(const float* map, int32_t F, int64_t J, srp_peak* peaks, void* stream) {
   if (map == nullptr || peaks == nullptr) return fail(SRP_ERR_INVALID_ARG, "NULL argument");
   if (F < 1) return fail(SRP_ERR_INVALID_ARG, "F must be >= 1");

@@ -21,6 +21,23 @@ __device__ __forceinline__ double norm3(double dx, double dy, double dz) {
   return s > 0.0 ? s * y : 0.0;
 }
 
+// sin(pi x) / pi for |x| <= 1/2: Taylor series of sin in float64,
+// x * sum_k (-1)^k pi^(2k) x^(2k) / (2k+1)!, truncated after x^17 (relative
+// truncation error < 1e-12 on the interval), then rounded once to float32.
+__device__ __forceinline__ float sinpi_over_pi(double x) {
+  const double u = x * x;
+  double p = 2.531217404137026e-07;  //  pi^16 / 17!
+  p = fma(p, u, -6.975873661656377e-06);  // -pi^14 / 15!
+  p = fma(p, u, 0.00014842879303107092);  //  pi^12 / 13!
+  p = fma(p, u, -0.0023460810354558226);  // -pi^10 / 11!
+  p = fma(p, u, 0.02614784781765479);  //  pi^8 / 9!
+  p = fma(p, u, -0.1907518241220842);  // -pi^6 / 7!
+  p = fma(p, u, 0.8117424252833535);  //  pi^4 / 5!
+  p = fma(p, u, -1.6449340668482264);  // -pi^2 / 3!
+  p = fma(p, u, 1.0);  // 1
+  return static_cast<float>(x * p);
+}
+
 // Unsigned key whose integer order is the float order of `v` (finite or inf),
 // with the candidate index in the low word so that, among equal values, the
 // LOWEST index has the LARGEST key. Key 0 means "no candidate yet".

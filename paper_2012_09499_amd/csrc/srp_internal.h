@@ -36,6 +36,24 @@ constexpr int kConvRunBins = 32;
 // Lag tiles of the GCC-sample kernel are 32 lags wide (one matrix-core tile).
 constexpr int kGccLagTile = 32;
 
+// Frames per array in one batched launch (srp_map_nyquist_batched).
+constexpr int kBatchMaxF = 8;
+
+// Device copy of one item of a batched launch.
+struct BatchItemDev {
+  const double* cand;        // [3][J]
+  const double* mic;         // [M][3]
+  const PairDesc* pairs;     // [P]
+  int64_t J;
+  int64_t xi_off;            // first sample of the item in the batch's sample arena
+  int S, P, F, far_field;
+  double inv_cT;
+  float* map;                // [F][J] or null
+  unsigned long long* keys;  // srp_peak[F] viewed as u64 pairs, or null
+  int block_begin;           // first workgroup of the item
+  int pad;
+};
+
 }  // namespace srp
 
 struct srp_geometry_s {
@@ -80,6 +98,8 @@ hipError_t launch_nyquist(const srp_geometry_s* g, const void* xi, int F, int dt
                           unsigned long long* keys, hipStream_t s);
 hipError_t launch_conventional(const srp_geometry_s* g, const float2* psi, int F, int dtype,
                                float* map, unsigned long long* keys, hipStream_t s);
+hipError_t launch_nyquist_batched(const BatchItemDev* d_items, int n_items, int total_blocks,
+                                  int max_f, const float* xi, hipStream_t s);
 hipError_t launch_peaks_init(srp_peak* peaks, int F, hipStream_t s);
 hipError_t launch_peaks_finalize(srp_peak* peaks, int F, hipStream_t s);
 hipError_t launch_argmax(const float* map, int F, int64_t J, unsigned long long* keys,
