@@ -33,10 +33,11 @@ namespace {
 
 constexpr int kStride = kNyqRunMax + 1;  // LDS row stride (odd) of the [frame][lag] tile
 
-// Above this many samples per frame the FP32 kernel sums in two levels: one
-// float32 accumulator over all S terms has a rounding error growing like
-// 2^-24 sqrt(S / 2), about 3.4e-6 at 16384 samples (the maps' 1e-5 bound).
-constexpr int64_t kNyqPlainSumMax = 16384;
+// Above this many samples per frame the FP32 kernel sums in two levels. The
+// relative error of one float32 accumulator over all S terms grows like
+// sqrt(S): measured 1.2e-5 at S = 609,344 (above the maps' 1e-5 bound), so
+// about 4e-6 at the 65,536 limit.
+constexpr int64_t kNyqPlainSumMax = 65536;
 
 struct NyqArgs {
   const double* cand;      // [3][J]

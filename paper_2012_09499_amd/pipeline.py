@@ -3,6 +3,9 @@
 Nyquist path: srp_cross_spectra -> srp_gcc_samples -> srp_map_nyquist.
 Conventional path: srp_cross_spectra -> srp_map_conventional.
 Every step is a libsrp kernel; buffers are torch tensors allocated once.
+The map and peaks returned by `nyquist` and `conventional` are views of the
+pipeline's own buffers: the next call overwrites them, so copy a result out
+before running the other path on the same pipeline.
 """
 from __future__ import annotations
 

@@ -71,8 +71,12 @@ CASES = {
                                               L=4096, F=2, seed=5, box=(1.2, 1.0, 0.6)),
     "m6_L1024_fmax4k_F4": lambda: WL.make_custom(M=6, J_shape=(7, 6, 5), L=1024, F=4, seed=6,
                                                  f_max=4000.0),
-    # S ~ 40k samples and 2KP ~ 280k terms: the two-level-sum kernel variants
+    # S ~ 48k samples (one-level FP32 sum near its limit), 2KP ~ 283k terms
+    # (two-level conventional sum)
     "m24_L1024_48k_F3": lambda: WL.make_custom(M=24, J_shape=(9, 7, 5), h=0.15, fs=48000.0,
+                                               L=1024, F=3, seed=9, box=(1.0, 1.0, 0.6)),
+    # S ~ 85k samples: the two-level-sum Nyquist kernel variant
+    "m32_L1024_48k_F3": lambda: WL.make_custom(M=32, J_shape=(9, 7, 5), h=0.15, fs=48000.0,
                                                L=1024, F=3, seed=9, box=(1.0, 1.0, 0.6)),
 }
 

@@ -243,6 +243,89 @@ def synth_frames(mic_xyz, sources, fs, L, F, c, snr_db, rng_sig, rng_noise,
     return np.ascontiguousarray(frames, dtype=np.float32)
 
 
+
+def hemisphere_direction(rng, n: int) -> np.ndarray:
+    """n propagation directions uniform over the half sphere r_z >= 0 that the
+    far-field candidate grid covers (uniform r_z and azimuth give a uniform
+    density on the sphere), generally between grid points."""
+    z = rng.random(n)
+    ph = 2.0 * np.pi * rng.random(n)
+    s = np.sqrt(1.0 - z * z)
+    return np.stack([s * np.cos(ph), s * np.sin(ph), z], axis=1)
+
+
+def _sphere_directions(rng, n: int) -> np.ndarray:
+    z = 2.0 * rng.random(n) - 1.0
+    ph = 2.0 * np.pi * rng.random(n)
+    s = np.sqrt(1.0 - z * z)
+    return np.stack([s * np.cos(ph), s * np.sin(ph), z], axis=1)
+
+
+def synth_far_scene(mic_xyz, direction, fs, L, F, c, snr_db, rng, t60: float = 0.6,
+                    drr_db: float = 0.0, n_refl: int = 64, noise: str = "diffuse"):
+    """Far-field scene [F][M][L] float32 closer to a reverberant room with
+    diffuse noise than `synth_frames`.
+
+    * Direct path: seeded white noise arriving along the unit propagation
+      direction `direction` (delay p_m . r / c, unit gain).
+    * Late reverberation: `n_refl` copies of the same signal from directions
+      uniform over the whole sphere, each with an extra delay uniform in
+      [2 ms, T60 / 2] and a Gaussian amplitude under the exponential envelope
+      exp(-3 ln(10) t / T60); their total energy is set so that
+      direct / reverberant energy is `drr_db`.
+    * Noise (`noise` = "diffuse"): a spherically isotropic field, made per
+      frequency by mixing independent white spectra with a square-root factor
+      of the coherence matrix sinc(2 f d_mm' / c) (normalised sinc), as in the
+      usual method for generating sensor signals in isotropic noise fields;
+      "white" gives independent sensor noise instead. Scaled to `snr_db`
+      against the mean reverberant-signal power.
+
+    With a sequence of SNRs the same signal and noise are mixed at each one
+    and a list of frame arrays is returned.
+    """
+    mic = np.asarray(mic_xyz, dtype=np.float64)
+    M = mic.shape[0]
+    n_keep = F * L
+    u0 = np.asarray(direction, dtype=np.float64).reshape(3)
+    ext = rng.uniform(0.002, 0.5 * t60, n_refl)
+    amp = rng.standard_normal(n_refl) * np.exp(-3.0 * math.log(10.0) * ext / t60)
+    amp *= math.sqrt(10.0 ** (-drr_db / 10.0) / float(np.sum(amp * amp)))
+    dirs = _sphere_directions(rng, n_refl)
+    tau = np.concatenate([(mic @ u0)[None, :] / c, ext[:, None] + (dirs @ mic.T) / c])  # [1+R][M]
+    gain = np.concatenate([[1.0], amp])
+    tau = tau - tau.min() + 2.0 / fs
+    pad = int(math.ceil(tau.max() * fs)) + 64
+    n_src = n_keep + pad
+    n_fft = 1 << int(math.ceil(math.log2(n_src + 64)))
+    freqs = np.fft.rfftfreq(n_fft, d=1.0 / fs)
+    spec = np.fft.rfft(rng.standard_normal(n_src), n_fft)
+    out = np.empty((M, n_keep), dtype=np.float64)
+    for m in range(M):
+        h = gain @ np.exp(-2j * np.pi * tau[:, m:m + 1] * freqs[None, :])
+        out[m] = np.fft.irfft(spec * h, n_fft)[pad:pad + n_keep]
+    p_sig = float(np.mean(out ** 2))
+    if noise == "diffuse":
+        d = np.linalg.norm(mic[:, None, :] - mic[None, :, :], axis=2)
+        gamma = np.sinc(2.0 * freqs[:, None, None] * d[None, :, :] / c)
+        lam, vec = np.linalg.eigh(gamma)
+        fac = vec * np.sqrt(np.clip(lam, 0.0, None))[:, None, :]
+        white = rng.standard_normal((freqs.size, M)) + 1j * rng.standard_normal((freqs.size, M))
+        nspec = np.einsum("fmk,fk->mf", fac, white)
+        nz = np.fft.irfft(nspec, n_fft, axis=1)[:, :n_keep]
+    elif noise == "white":
+        nz = rng.standard_normal((M, n_keep))
+    else:
+        raise ValueError(f"unknown noise {noise!r}")
+    nz *= 1.0 / math.sqrt(float(np.mean(nz ** 2)))
+
+    def mix(snr):
+        fr = (out + math.sqrt(p_sig / (10.0 ** (snr / 10.0))) * nz).reshape(M, F, L)
+        return np.ascontiguousarray(fr.transpose(1, 0, 2), dtype=np.float32)
+
+    if np.ndim(snr_db) == 0:
+        return mix(float(snr_db))
+    return [mix(float(snr)) for snr in snr_db]
+
 CONFIG_NAMES = {
     1: "cfg1-plain-4mic-2500cand",
     2: "cfg2-room-16mic-576kcand-500fr",
