@@ -22,6 +22,7 @@ import argparse
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -85,9 +86,11 @@ def cpu_baseline(wl, n_cand: int, seed: int = 0):
     return info, idx, ref
 
 
-def serving_run(seconds: float, rate_per_array: float = 31.25, seed: int = 4):
+def serving_run(seconds: float, rate_per_array: float = 31.25, seed: int = 4,
+                dtype: str = "fp32"):
     """The serving workload: 64 arrays (M in {4, 8, 16, 32}, J log-uniform in
-    [1e4, 2e6]), Poisson frame arrivals, continuous batching (FP32)."""
+    [1e4, 2e6]), Poisson frame arrivals, continuous batching; maps in FP32
+    (vector units) or BF16/FP16 (matrix cores)."""
     import torch
     import workloads as WL
     from paper_2012_09499_amd import serving as SV
@@ -95,7 +98,7 @@ def serving_run(seconds: float, rate_per_array: float = 31.25, seed: int = 4):
     arrays = WL.serving_arrays(64, seed=seed)
     fs, L, c = 16000.0, 1024, 343.0
     rng = np.random.default_rng(seed)
-    srv = SV.SrpServer()
+    srv = SV.SrpServer(dtype=dtype)
     frames = {}
     t_setup = time.perf_counter()
     for a in arrays:
@@ -136,7 +139,7 @@ def serving_run(seconds: float, rate_per_array: float = 31.25, seed: int = 4):
     Js = [a["grid"].J for a in arrays]
     Ms = [len(a["mic_xyz"]) for a in arrays]
     st.update({"offered_frames_per_s": len(arrivals) / seconds, "seconds": seconds,
-               "wall_seconds": span, "arrays": len(arrays), "dtype": "f32",
+               "wall_seconds": span, "arrays": len(arrays),
                "J_range": [int(min(Js)), int(max(Js))], "mic_counts": sorted(set(Ms)),
                "setup_seconds": t_setup})
     return st
@@ -230,6 +233,10 @@ def main():
     ap.add_argument("--cpu-candidates", type=int, default=40000)
     ap.add_argument("--serving-seconds", type=float, default=10.0,
                     help="length of the serving run (0 skips it)")
+    ap.add_argument("--serving-leg", choices=("fp32", "bf16", "fp16"), default=None,
+                    help="only run the serving workload in this precision (one JSON line)")
+    ap.add_argument("--serving-rate", type=float, default=31.25,
+                    help="frames/s per array of the serving workload")
     ap.add_argument("--paper-standin", action="store_true",
                     help="only run the stand-in for the paper's far-field experiment")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -246,6 +253,10 @@ def main():
     import workloads as WL
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.serving_leg:
+        print(json.dumps(serving_run(args.serving_seconds, rate_per_array=args.serving_rate,
+                                     dtype=args.serving_leg)), flush=True)
+        return
     if args.paper_standin:
         print(json.dumps({"paper_standin": paper_standin()}))
         return
@@ -386,11 +397,26 @@ def main():
               file=sys.stderr, flush=True)
 
     if args.serving_seconds > 0:
-        st = serving_run(args.serving_seconds)
-        out["serving"] = st
-        print(f"[bench] serving: {st['frames_per_s']:.0f} frames/s done of "
-              f"{st['offered_frames_per_s']:.0f} offered, p50 {st['latency_ms_p50']:.1f} ms, "
-              f"p99 {st['latency_ms_p99']:.1f} ms", file=sys.stderr, flush=True)
+        # the offered load (31.25 frames/s per array, 2,007 frames/s in all) in
+        # FP32 and BF16, then 8x that load for a third of the time: the frames/s
+        # completed there is the server's capacity in each precision
+        legs = [("serving", "fp32", 31.25, args.serving_seconds),
+                ("serving_bf16", "bf16", 31.25, args.serving_seconds),
+                ("serving_capacity_fp32", "fp32", 250.0, args.serving_seconds / 3.0),
+                ("serving_capacity_bf16", "bf16", 250.0, args.serving_seconds / 3.0)]
+        for key, sdt, rate, secs in legs:
+            # each serving configuration runs in a process of its own, as a
+            # deployed server would (a child process, not an exec)
+            cmd = [sys.executable, os.path.abspath(__file__), "--serving-leg", sdt,
+                   "--serving-seconds", str(secs), "--serving-rate", str(rate)]
+            r = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
+            if r.returncode != 0:
+                raise RuntimeError(f"serving leg {key} failed:\n{r.stderr[-2000:]}")
+            st = json.loads(r.stdout.strip().splitlines()[-1])
+            out[key] = st
+            print(f"[bench] {key}: {st['frames_per_s']:.0f} frames/s done of "
+                  f"{st['offered_frames_per_s']:.0f} offered, p50 {st['latency_ms_p50']:.1f} ms, "
+                  f"p99 {st['latency_ms_p99']:.1f} ms", file=sys.stderr, flush=True)
 
     print(json.dumps(out), flush=True)
 

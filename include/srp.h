@@ -178,9 +178,9 @@ srp_status srp_map_nyquist(const srp_geometry_t* g, const void* xi, int32_t F, i
 /* One item of a batched Nyquist launch: an array and its frames of the batch. */
 typedef struct {
   const srp_geometry_t* g;   /* the array                                            */
-  int64_t xi_offset;         /* index (in floats) of the item's first sample in xi;  */
+  int64_t xi_offset;         /* index (in elements) of the item's first sample in xi; */
                              /* the item's samples are F x S (srp_gcc_samples layout) */
-  int32_t F;                 /* frames of the item, 1 <= F <= 8                      */
+  int32_t F;                 /* frames of the item: 1..8 (SRP_FP32), 1..16 (BF16/FP16) */
   int32_t reserved;
   float* map;                /* device F x J float32, written; may be NULL if peaks is not */
   srp_peak* peaks;           /* device F, written; may be NULL if map is not         */
@@ -191,18 +191,24 @@ srp_status srp_map_nyquist_batched_workspace(int32_t n_items, size_t* bytes);
 
 /* Nyquist maps of many arrays in one ragged launch (Eq. SRPapprox summed over
  * pairs, Eq. SRP_T_IFT), for serving: arrays of different microphone counts,
- * windows and grids, each with a few frames. Same result definition and
- * accuracy as srp_map_nyquist; computed on the vector units in float32 (with
- * one to eight frames per array the weights are formed once per candidate
- * and lag and used by those frames only).
+ * windows and grids, each with a few frames. Same result definition as
+ * srp_map_nyquist.
  *   items      host, n_items entries (read before the call returns)
- *   xi         device float32 sample arena holding every item's samples
- *   dtype      SRP_FP32
+ *   xi         device sample arena holding every item's samples, stored as
+ *              float (SRP_FP32), bfloat16 (SRP_BF16) or half (SRP_FP16)
+ *   dtype      SRP_FP32: float32 on the vector units (with one to eight
+ *              frames per array the weights are formed once per candidate and
+ *              lag and used by those frames only), the accuracy of
+ *              srp_map_nyquist in FP32;
+ *              SRP_BF16 / SRP_FP16: weights in that type on the matrix cores
+ *              (16 frames x 16 candidates x 32 lags per instruction), float32
+ *              accumulation, the accuracy of srp_map_nyquist in that type; the
+ *              arena must be 16-byte aligned and every xi_offset a multiple of 8
  *   workspace  device, >= srp_map_nyquist_batched_workspace bytes; holds the
  *              item table until the launch has finished (do not reuse it for
  *              another batch on another stream before then)
  * All items must live on one device. */
-srp_status srp_map_nyquist_batched(const srp_batch_item* items, int32_t n_items, const float* xi,
+srp_status srp_map_nyquist_batched(const srp_batch_item* items, int32_t n_items, const void* xi,
                                    int32_t dtype, void* workspace, size_t workspace_bytes,
                                    void* stream);
 

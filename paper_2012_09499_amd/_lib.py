@@ -33,7 +33,12 @@ EXPORTS = ("srp_pair_layout", "srp_geometry", "srp_geometry_query", "srp_geometr
            "srp_cross_spectra_workspace", "srp_cross_spectra", "srp_gcc_samples",
            "srp_map_conventional", "srp_map_nyquist", "srp_map_nyquist_batched_workspace",
            "srp_map_nyquist_batched", "srp_argmax", "srp_last_error", "srp_version")
-BATCH_MAX_F = 8
+BATCH_MAX_F = 8            # frames per item of a batched launch, FP32 samples
+BATCH_MAX_F_MX = 16        # ... BF16 / FP16 samples (matrix-core tile)
+
+
+def batch_max_frames(dtype: str) -> int:
+    return BATCH_MAX_F if dtype == "fp32" else BATCH_MAX_F_MX
 
 
 class SrpError(RuntimeError):
@@ -281,15 +286,19 @@ def batched_workspace_bytes(n_items: int) -> int:
     return int(n.value)
 
 
-def map_nyquist_batched(items, xi_arena, workspace, stream=None):
+def map_nyquist_batched(items, xi_arena, workspace, stream=None, dtype: str = "fp32"):
     """One ragged launch over many arrays (srp_map_nyquist_batched).
 
     items: list of (Geometry, xi_offset, F, map tensor or None, peaks tensor or None);
-    xi_arena: float32 CUDA tensor holding every item's samples; workspace: CUDA
-    uint8 tensor of at least batched_workspace_bytes(len(items)) bytes.
+    xi_arena: CUDA tensor holding every item's samples, float32 for dtype "fp32",
+    bfloat16 / float16 for "bf16" / "fp16" (then every xi_offset is a multiple
+    of 8); workspace: CUDA uint8 tensor of at least
+    batched_workspace_bytes(len(items)) bytes.
     """
     import torch
-    _need_cuda(xi_arena, "xi_arena", torch.float32)
+    if dtype not in ("fp32", "bf16", "fp16"):
+        raise ValueError(f"batched dtype must be fp32, bf16 or fp16, not {dtype!r}")
+    _need_cuda(xi_arena, "xi_arena", sample_torch_dtype(dtype))
     n = len(items)
     arr = (BatchItem * n)()
     for i, (g, off, F, m, pk) in enumerate(items):
@@ -302,7 +311,7 @@ def map_nyquist_batched(items, xi_arena, workspace, stream=None):
         arr[i].F = int(F)
         arr[i].map = m.data_ptr() if m is not None else None
         arr[i].peaks = pk.data_ptr() if pk is not None else None
-    _check(lib().srp_map_nyquist_batched(arr, n, xi_arena.data_ptr(), DTYPES["fp32"],
+    _check(lib().srp_map_nyquist_batched(arr, n, xi_arena.data_ptr(), DTYPES[dtype],
                                          workspace.data_ptr(),
                                          workspace.numel() * workspace.element_size(),
                                          _stream_handle(stream)))

@@ -17,14 +17,22 @@
 namespace srp {
 namespace {
 
-template <int FT, typename OutT>
-__global__ __launch_bounds__(64) void gcc_samples_kernel(
+// Bins are split over the KS waves of a workgroup (each wave sums a
+// contiguous range of bins, so short transforms and few frames still give many
+// waves); the partial tiles are added in LDS in wave order, so the result
+// does not depend on timing. Each wave prefetches the next group of bins while
+// the matrix cores consume the current one.
+template <int FT, typename OutT, int KS>
+__global__ __launch_bounds__(64 * KS) void gcc_samples_kernel(
     const float2* __restrict__ psi, const float* __restrict__ binw,
     const float2* __restrict__ table, int nw, int h_max, const LagRun* __restrict__ tiles,
     const PairDesc* __restrict__ pairs, int F, int P, int K, int S, OutT* __restrict__ xi) {
+  constexpr int U = 4;  // bins per group
+  __shared__ floatx16 part[(KS > 1 ? KS - 1 : 1) * FT * 64];
   const LagRun tl = tiles[blockIdx.x];
   const PairDesc pd = pairs[tl.p];
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
   const int cl = lane & 31;
   const int g = lane >> 5;
   const int fbase = blockIdx.y * 32 * FT;
@@ -47,28 +55,67 @@ __global__ __launch_bounds__(64) void gcc_samples_kernel(
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[ft][r] = 0.0f;
 
-  int k = 0;
-  for (; k + 4 <= K; k += 4) {
-    float b[4], a[4][FT];
+  // this wave's bins [k0, k1)
+  const int per = (K + KS - 1) / KS;
+  const int k0 = wave * per;
+  const int k1 = k0 + per < K ? k0 + per : K;
+  int k = k0;
+  if (k + U <= k1) {
+    float b[U], a[U][FT];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < U; ++u) {
       b[u] = brow[(size_t)(k + u) * bstride];
       const float wk = binw[k + u];
 #pragma unroll
       for (int ft = 0; ft < FT; ++ft) a[u][ft] = arow[ft][2 * (k + u)] * wk;
     }
+    for (; k + 2 * U <= k1; k += U) {
+      float nb[U], na[U][FT];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < U; ++u) {
+        nb[u] = brow[(size_t)(k + U + u) * bstride];
+        const float wk = binw[k + U + u];
+#pragma unroll
+        for (int ft = 0; ft < FT; ++ft) na[u][ft] = arow[ft][2 * (k + U + u)] * wk;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int ft = 0; ft < FT; ++ft)
+          acc[ft] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[u][ft], b[u], acc[ft], 0, 0, 0);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        b[u] = nb[u];
+#pragma unroll
+        for (int ft = 0; ft < FT; ++ft) a[u][ft] = na[u][ft];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int ft = 0; ft < FT; ++ft)
         acc[ft] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[u][ft], b[u], acc[ft], 0, 0, 0);
+    k += U;
   }
-  for (; k < K; ++k) {
+  for (; k < k1; ++k) {
     const float b = brow[(size_t)k * bstride];
     const float wk = binw[k];
 #pragma unroll
     for (int ft = 0; ft < FT; ++ft)
       acc[ft] = __builtin_amdgcn_mfma_f32_32x32x2f32(arow[ft][2 * k] * wk, b, acc[ft], 0, 0, 0);
+  }
+
+  if (KS > 1) {
+    if (wave > 0) {
+#pragma unroll
+      for (int ft = 0; ft < FT; ++ft) part[((wave - 1) * FT + ft) * 64 + lane] = acc[ft];
+    }
+    __syncthreads();
+    if (wave != 0) return;
+#pragma unroll
+    for (int w = 1; w < KS; ++w)
+#pragma unroll
+      for (int ft = 0; ft < FT; ++ft) acc[ft] += part[((w - 1) * FT + ft) * 64 + lane];
   }
 
   // D[frame][lag]: lane (cl, g), register r holds frame 8 (r / 4) + 4 g + r % 4, lag cl.
@@ -93,27 +140,35 @@ __global__ __launch_bounds__(64) void gcc_samples_kernel(
 
 }  // namespace
 
+template <int FT, int KS, typename OutT>
+void launch_gcc(const srp_geometry_s* g, const float2* psi, int F, OutT* xi, hipStream_t s) {
+  const int n_tiles = static_cast<int>(g->gcc_tiles.size());
+  const dim3 grid(n_tiles, (F + 32 * FT - 1) / (32 * FT));
+  hipLaunchKernelGGL((gcc_samples_kernel<FT, OutT, KS>), grid, dim3(64 * KS), 0, s, psi,
+                     g->d_binw, g->d_gcc_table, g->gcc_nw, g->info.h_max, g->d_gcc_tiles,
+                     g->d_pairs, F, g->info.P, g->info.K, static_cast<int>(g->info.S), xi);
+}
+
+// Up to 32 frames (serving batches): one 32-frame tile per wave, bins over 8
+// waves; more frames: two 32-frame tiles per wave, bins over 4 waves.
+template <typename OutT>
+void launch_gcc_any(const srp_geometry_s* g, const float2* psi, int F, OutT* xi, hipStream_t s) {
+  if (F <= 32)
+    launch_gcc<1, 8>(g, psi, F, xi, s);
+  else
+    launch_gcc<2, 4>(g, psi, F, xi, s);
+}
+
 hipError_t launch_gcc_samples(const srp_geometry_s* g, const float2* psi, int F, int dtype,
                               void* xi, hipStream_t s) {
-  constexpr int FT = 2;
-  const int n_tiles = static_cast<int>(g->gcc_tiles.size());
-  dim3 grid(n_tiles, (F + 32 * FT - 1) / (32 * FT));
-  const int S = static_cast<int>(g->info.S);
-  if (dtype == SRP_FP32) {
-    hipLaunchKernelGGL((gcc_samples_kernel<FT, float>), grid, dim3(64), 0, s, psi, g->d_binw,
-                       g->d_gcc_table, g->gcc_nw, g->info.h_max, g->d_gcc_tiles, g->d_pairs, F,
-                       g->info.P, g->info.K, S, static_cast<float*>(xi));
-  } else if (dtype == SRP_BF16) {
-    hipLaunchKernelGGL((gcc_samples_kernel<FT, __bf16>), grid, dim3(64), 0, s, psi, g->d_binw,
-                       g->d_gcc_table, g->gcc_nw, g->info.h_max, g->d_gcc_tiles, g->d_pairs, F,
-                       g->info.P, g->info.K, S, static_cast<__bf16*>(xi));
-  } else if (dtype == SRP_FP16) {
-    hipLaunchKernelGGL((gcc_samples_kernel<FT, _Float16>), grid, dim3(64), 0, s, psi, g->d_binw,
-                       g->d_gcc_table, g->gcc_nw, g->info.h_max, g->d_gcc_tiles, g->d_pairs, F,
-                       g->info.P, g->info.K, S, static_cast<_Float16*>(xi));
-  } else {
+  if (dtype == SRP_FP32)
+    launch_gcc_any(g, psi, F, static_cast<float*>(xi), s);
+  else if (dtype == SRP_BF16)
+    launch_gcc_any(g, psi, F, static_cast<__bf16*>(xi), s);
+  else if (dtype == SRP_FP16)
+    launch_gcc_any(g, psi, F, static_cast<_Float16*>(xi), s);
+  else
     return hipErrorNotSupported;
-  }
   return hipGetLastError();
 }
 

@@ -6,6 +6,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 #include <new>
 #include <string>
@@ -393,49 +394,69 @@ srp_status srp_map_nyquist_batched_workspace(int32_t n_items, size_t* bytes) {
   return SRP_OK;
 }
 
-srp_status srp_map_nyquist_batched(const srp_batch_item* items, int32_t n_items, const float* xi,
+srp_status srp_map_nyquist_batched(const srp_batch_item* items, int32_t n_items, const void* xi,
                                    int32_t dtype, void* workspace, size_t workspace_bytes,
                                    void* stream) {
   if (items == nullptr || xi == nullptr || workspace == nullptr)
     return fail(SRP_ERR_INVALID_ARG, "srp_map_nyquist_batched: NULL argument");
   if (n_items < 1) return fail(SRP_ERR_INVALID_ARG, "n_items must be >= 1");
-  if (dtype != SRP_FP32) return fail(SRP_ERR_UNSUPPORTED, "the batched path computes in FP32");
+  if (dtype != SRP_FP32 && dtype != SRP_BF16 && dtype != SRP_FP16)
+    return fail(SRP_ERR_UNSUPPORTED, "batched samples must be FP32, BF16 or FP16");
+  const bool mx = dtype != SRP_FP32;
+  const int max_frames = mx ? kBatchMaxFMx : kBatchMaxF;
+  if (mx && (reinterpret_cast<uintptr_t>(xi) & 15) != 0)
+    return fail(SRP_ERR_INVALID_ARG, "BF16/FP16 sample arena must be 16-byte aligned");
   if (workspace_bytes < (size_t)n_items * sizeof(BatchItemDev))
     return fail(SRP_ERR_INVALID_ARG, "workspace too small");
-  std::vector<BatchItemDev> dev(n_items);
-  int64_t blocks = 0;
-  int max_f = 1;
+  // vector-unit items first, then matrix-core items; block_begin per group
+  std::vector<BatchItemDev> dev;
+  dev.reserve(n_items);
+  int64_t blocks[2] = {0, 0};
+  int n_group[2] = {0, 0};
+  int max_f_vec = 1;
   int device = -1;
-  for (int i = 0; i < n_items; ++i) {
-    const srp_batch_item& it = items[i];
-    if (it.g == nullptr) return fail(SRP_ERR_INVALID_ARG, "item geometry is NULL");
-    if (it.F < 1 || it.F > kBatchMaxF)
-      return fail(SRP_ERR_INVALID_ARG, "item F must be in [1, 8]");
-    if (it.map == nullptr && it.peaks == nullptr)
-      return fail(SRP_ERR_INVALID_ARG, "item map and peaks are both NULL");
-    if (it.xi_offset < 0) return fail(SRP_ERR_INVALID_ARG, "negative xi_offset");
-    if (device >= 0 && it.g->device != device)
-      return fail(SRP_ERR_INVALID_ARG, "items on different devices");
-    device = it.g->device;
-    BatchItemDev& d = dev[i];
-    d.cand = it.g->d_cand;
-    d.mic = it.g->d_mic;
-    d.pairs = it.g->d_pairs;
-    d.J = it.g->info.J;
-    d.xi_off = it.xi_offset;
-    d.S = static_cast<int>(it.g->info.S);
-    d.P = it.g->info.P;
-    d.F = it.F;
-    d.far_field = it.g->info.field == SRP_FAR_FIELD;
-    d.inv_cT = it.g->inv_cT;
-    d.map = it.map;
-    d.keys = reinterpret_cast<unsigned long long*>(it.peaks);
-    d.block_begin = static_cast<int>(blocks);
-    d.pad = 0;
-    blocks += (d.J + 255) / 256;
-    max_f = it.F > max_f ? it.F : max_f;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int i = 0; i < n_items; ++i) {
+      const srp_batch_item& it = items[i];
+      if (pass == 0) {
+        if (it.g == nullptr) return fail(SRP_ERR_INVALID_ARG, "item geometry is NULL");
+        if (it.F < 1 || it.F > max_frames)
+          return fail(SRP_ERR_INVALID_ARG,
+                      mx ? "item F must be in [1, 16]" : "item F must be in [1, 8]");
+        if (it.map == nullptr && it.peaks == nullptr)
+          return fail(SRP_ERR_INVALID_ARG, "item map and peaks are both NULL");
+        if (it.xi_offset < 0) return fail(SRP_ERR_INVALID_ARG, "negative xi_offset");
+        if (mx && it.xi_offset % kSampleAlign != 0)
+          return fail(SRP_ERR_INVALID_ARG, "BF16/FP16 xi_offset must be a multiple of 8");
+        if (device >= 0 && it.g->device != device)
+          return fail(SRP_ERR_INVALID_ARG, "items on different devices");
+        device = it.g->device;
+      }
+      const int grp = (mx && it.F > kBatchVecMaxF) ? 1 : 0;
+      if (grp != pass) continue;
+      BatchItemDev d;
+      d.cand = it.g->d_cand;
+      d.mic = it.g->d_mic;
+      d.pairs = it.g->d_pairs;
+      d.J = it.g->info.J;
+      d.xi_off = it.xi_offset;
+      d.S = static_cast<int>(it.g->info.S);
+      d.P = it.g->info.P;
+      d.F = it.F;
+      d.far_field = it.g->info.field == SRP_FAR_FIELD;
+      d.inv_cT = it.g->inv_cT;
+      d.map = it.map;
+      d.keys = reinterpret_cast<unsigned long long*>(it.peaks);
+      d.block_begin = static_cast<int>(blocks[grp]);
+      d.pad = 0;
+      dev.push_back(d);
+      blocks[grp] += (d.J + 255) / 256;
+      ++n_group[grp];
+      if (grp == 0) max_f_vec = it.F > max_f_vec ? it.F : max_f_vec;
+    }
   }
-  if (blocks >= (int64_t(1) << 31)) return fail(SRP_ERR_INVALID_ARG, "batch too large");
+  if (blocks[0] >= (int64_t(1) << 31) || blocks[1] >= (int64_t(1) << 31))
+    return fail(SRP_ERR_INVALID_ARG, "batch too large");
   DeviceGuard dg(device);
   if (!dg.ok) return fail(SRP_ERR_DEVICE, "cannot select the items' device");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -443,8 +464,9 @@ srp_status srp_map_nyquist_batched(const srp_batch_item* items, int32_t n_items,
   hipError_t e = hipMemcpyAsync(workspace, dev.data(), dev.size() * sizeof(BatchItemDev),
                                 hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
-    e = launch_nyquist_batched(static_cast<const BatchItemDev*>(workspace), n_items,
-                               static_cast<int>(blocks), max_f, xi, s);
+    e = launch_nyquist_batched(static_cast<const BatchItemDev*>(workspace), n_group[0],
+                               static_cast<int>(blocks[0]), max_f_vec, n_group[1],
+                               static_cast<int>(blocks[1]), dtype, xi, s);
   if (e != hipSuccess) return device_fail(e, "map_nyquist_batched");
   return SRP_OK;
 }

@@ -36,8 +36,13 @@ constexpr int kConvRunBins = 32;
 // Lag tiles of the GCC-sample kernel are 32 lags wide (one matrix-core tile).
 constexpr int kGccLagTile = 32;
 
-// Frames per array in one batched launch (srp_map_nyquist_batched).
+// Frames per array in one batched launch (srp_map_nyquist_batched): FP32
+// samples (vector units) and BF16/FP16 samples (16-frame matrix-core tile).
 constexpr int kBatchMaxF = 8;
+constexpr int kBatchMaxFMx = 16;
+// BF16/FP16 items with at most this many frames run on the vector units (the
+// matrix-core tile costs the same for 1 and for 16 frames).
+constexpr int kBatchVecMaxF = 2;
 
 // Device copy of one item of a batched launch.
 struct BatchItemDev {
@@ -98,8 +103,11 @@ hipError_t launch_nyquist(const srp_geometry_s* g, const void* xi, int F, int dt
                           unsigned long long* keys, hipStream_t s);
 hipError_t launch_conventional(const srp_geometry_s* g, const float2* psi, int F, int dtype,
                                float* map, unsigned long long* keys, hipStream_t s);
-hipError_t launch_nyquist_batched(const BatchItemDev* d_items, int n_items, int total_blocks,
-                                  int max_f, const float* xi, hipStream_t s);
+// Items [0, n_vec) go to the vector-unit kernel, [n_vec, n_vec + n_mx) to the
+// matrix-core kernel (BF16/FP16 only); block_begin counts within each group.
+hipError_t launch_nyquist_batched(const BatchItemDev* d_items, int n_vec, int blocks_vec,
+                                  int max_f_vec, int n_mx, int blocks_mx, int dtype,
+                                  const void* xi, hipStream_t s);
 hipError_t launch_peaks_init(srp_peak* peaks, int F, hipStream_t s);
 hipError_t launch_peaks_finalize(srp_peak* peaks, int F, hipStream_t s);
 hipError_t launch_argmax(const float* map, int F, int64_t J, unsigned long long* keys,

@@ -8,9 +8,12 @@ candidate grids) arrive as requests. The server
   memory budget; arrays that do not fit wait and are admitted when others
   close;
 * runs a loop that, whenever one of its batch slots is free, takes every
-  pending frame (up to 8 per array) into a batch: one host-to-device copy of
-  the frames, per-array srp_cross_spectra and srp_gcc_samples, then one ragged
-  srp_map_nyquist_batched launch for all arrays of the batch;
+  pending frame (up to 8 per array in FP32, 16 in BF16/FP16) into a batch: one
+  host-to-device copy of the frames, per-array srp_cross_spectra and
+  srp_gcc_samples, then one ragged srp_map_nyquist_batched launch for all
+  arrays of the batch;
+* computes in FP32 (vector units) or BF16/FP16 (matrix cores, samples stored
+  in that type, float32 accumulation), chosen per server;
 * keeps two batch slots on two HIP streams, so a batch is assembled and its
   spectra run while the previous batch's maps are still on the GPU; requests
   that arrive meanwhile join the next batch (continuous batching);
@@ -52,21 +55,16 @@ class Request:
 
 
 class _Array:
-    def __init__(self, array_id, geom: S.Geometry, max_f: int):
+    def __init__(self, array_id, geom: S.Geometry):
         self.id = array_id
         self.g = geom
         self.M, self.P, self.K, self.L, self.S, self.J = geom.M, geom.P, geom.K, geom.L, geom.S, geom.J
         self.pending: collections.deque = collections.deque()
-        # per-slot device bytes this array may take in one batch
-        f = max_f
-        self.slot_bytes = f * (self.M * self.L * 4 + self.M * self.K * 8 + self.P * self.K * 8
-                               + self.S * 4 + 16) + 4 * 256
-        self.geom_bytes = 24 * self.J + 8 * self.K * (2 * geom.h_max + 33) + 64 * self.P + 4096
 
 
-def footprint(geom_J, M, K, L, S, P, h_max, max_f=S.BATCH_MAX_F, slots=2):
+def footprint(geom_J, M, K, L, S, P, h_max, max_f=S.BATCH_MAX_F, slots=2, sample_bytes=4):
     """Device bytes an array occupies in the server (geometry + its share of each slot)."""
-    slot = max_f * (M * L * 4 + M * K * 8 + P * K * 8 + S * 4 + 16) + 4 * 256
+    slot = max_f * (M * L * 4 + M * K * 8 + P * K * 8 + S * sample_bytes + 16) + 4 * 256
     geom = 24 * geom_J + 8 * K * (2 * h_max + 33) + 64 * P + 4096
     return geom + slots * slot
 
@@ -101,15 +99,22 @@ class _Slot:
 
 class SrpServer:
     def __init__(self, memory_budget: Optional[int] = None, device="cuda:0",
-                 max_frames_per_array: int = S.BATCH_MAX_F, slots: int = 2):
+                 max_frames_per_array: Optional[int] = None, slots: int = 2,
+                 dtype: str = "fp32"):
         import torch
+        if dtype not in ("fp32", "bf16", "fp16"):
+            raise ValueError(f"dtype must be fp32, bf16 or fp16, not {dtype!r}")
+        self.dtype = dtype
+        self.sample_dtype = S.sample_torch_dtype(dtype)
+        self.sample_bytes = 4 if dtype == "fp32" else 2
         self.device = torch.device(device)
         if memory_budget is None:
             free, _ = torch.cuda.mem_get_info(self.device)
             memory_budget = int(0.8 * free)
         self.budget = int(memory_budget)
         self.used = 0
-        self.max_f = min(int(max_frames_per_array), S.BATCH_MAX_F)
+        cap = S.batch_max_frames(dtype)
+        self.max_f = cap if max_frames_per_array is None else min(int(max_frames_per_array), cap)
         self.arrays: Dict[int, _Array] = {}
         self.waiting: collections.OrderedDict = collections.OrderedDict()
         self.slots = [_Slot(self.device) for _ in range(slots)]
@@ -130,7 +135,7 @@ class SrpServer:
         M = len(mic_xyz)
         K = L // 2 + 1
         need = footprint(len(candidates), M, K, L, Ssz, M * (M - 1) // 2,
-                         int(N_p.max()) + n_aux, self.max_f, len(self.slots))
+                         int(N_p.max()) + n_aux, self.max_f, len(self.slots), self.sample_bytes)
         if need > self.budget:
             raise ValueError(f"array {array_id} needs {need} bytes, more than the whole budget")
         if self.used + need > self.budget:
@@ -143,7 +148,7 @@ class SrpServer:
         g = S.Geometry(spec["mic_xyz"], spec["candidates"], fs=spec["fs"], L=spec["L"],
                        c=spec["c"], n_aux=spec["n_aux"], field=spec["field"],
                        window=spec["window"])
-        a = _Array(array_id, g, self.max_f)
+        a = _Array(array_id, g)
         a.need = need
         self.arrays[array_id] = a
         self.used += need
@@ -256,7 +261,7 @@ class SrpServer:
         frames = slot.buf("frames", fr_off, torch.float32)
         ws = slot.buf("ws", ws_off, torch.uint8)
         psi = slot.buf("psi", psi_off, torch.complex64)
-        xi = slot.buf("xi", xi_off, torch.float32)
+        xi = slot.buf("xi", xi_off, self.sample_dtype)
         peaks = slot.buf("peaks", 2 * pk_off, torch.int64)
         item_ws = slot.buf("items", S.batched_workspace_bytes(len(plan)), torch.uint8)
         items = []
@@ -270,10 +275,10 @@ class SrpServer:
                     S.cross_spectra(a.g, fv, out=pv, workspace=ws[wo:wo + F * a.M * a.K * 8],
                                     stream=slot.stream)
                     xv = xi[xo:xo + F * a.S].view(F, a.S)
-                    S.gcc_samples(a.g, pv, out=xv, stream=slot.stream)
+                    S.gcc_samples(a.g, pv, out=xv, dtype=self.dtype, stream=slot.stream)
                     items.append((a.g, xo, F, None, peaks[2 * ko:2 * (ko + F)].view(F, 2)))
                     reqs_all.extend(reqs)
-                S.map_nyquist_batched(items, xi, item_ws, stream=slot.stream)
+                S.map_nyquist_batched(items, xi, item_ws, stream=slot.stream, dtype=self.dtype)
                 if slot.cap.get("peaks_host", 0) < 2 * pk_off:
                     slot.bufs["peaks_host"] = torch.empty(max(2 * pk_off, 256), dtype=torch.int64,
                                                           pin_memory=True)
@@ -311,4 +316,5 @@ class SrpServer:
             "mean_frames_per_batch": float(np.mean(self.batch_frames)) if self.batch_frames else 0,
             "arrays_admitted": len(self.arrays), "arrays_waiting": len(self.waiting),
             "memory_budget_bytes": self.budget, "memory_used_bytes": self.used,
+            "dtype": self.dtype, "max_frames_per_array": self.max_f,
         }
