@@ -25,6 +25,8 @@
 //   step s of a lag run covers lags t = 2s (k = 0, lanes 0-31) and 2s + 1 (k = 1, lanes 32-63);
 //   A = samples staged in LDS as [frame][lag]; B = weights (lane = candidate);
 //   epilogue: x2, optional map store, argmax via LDS u64 max + one global atomic per frame.
+#include <type_traits>
+
 #include "srp_device.h"
 #include "srp_internal.h"
 
@@ -47,6 +49,7 @@ struct NyqArgs {
   int n_runs;
   const float* xi;         // [F][S]
   int F;
+  int f_base;              // first frame of this launch's frame blocks
   int S;
   int64_t J;
   double inv_cT;
@@ -212,7 +215,7 @@ void nyquist_f32_kernel(NyqArgs a, const double* __restrict__ mic,
   const int cl = lane & 31;
   const int g = lane >> 5;
   const int64_t jb = (int64_t)blockIdx.x * JB + wave * JW;
-  const int f0 = blockIdx.y * FB;
+  const int f0 = a.f_base + blockIdx.y * FB;
   const int nrows = a.F - f0 < FB ? a.F - f0 : FB;
 
   LaneState<CT> st;
@@ -466,7 +469,7 @@ void nyquist_mx_kernel(NyqArgs a, const T* __restrict__ xi, const double* __rest
   const int cl = lane & 31;
   const int g = lane >> 5;
   const int64_t jb = (int64_t)blockIdx.x * JB + wave * 32;
-  const int f0 = blockIdx.y * FB;
+  const int f0 = a.f_base + blockIdx.y * FB;
   const int nrows = a.F - f0 < FB ? a.F - f0 : FB;
 
   LaneState<1> st;
@@ -614,6 +617,36 @@ __global__ __launch_bounds__(256) void nyquist_f64_kernel(NyqArgs a) {
 
 }  // namespace
 
+// Frame blocks of FTMAX 32-frame tiles, then (if F is not a multiple of the
+// block) one more launch whose single block has just enough tiles for the
+// remaining frames, so no matrix-core work is spent on frames past F.
+template <int FTMAX, typename Launch>
+void launch_frame_blocks(int F, const NyqArgs& a, Launch&& launch) {
+  constexpr int FB = 32 * FTMAX;
+  const int full = F / FB;
+  if (full > 0) {
+    NyqArgs b = a;
+    b.f_base = 0;
+    launch(std::integral_constant<int, FTMAX>(), b, full);
+  }
+  const int rem = F - full * FB;
+  if (rem == 0) return;
+  NyqArgs b = a;
+  b.f_base = full * FB;
+  const int tiles = (rem + 31) / 32;  // 1 .. FTMAX (FTMAX <= 8)
+  static_assert(FTMAX <= 8, "tail dispatch covers up to 8 tiles");
+  switch (tiles) {
+    case 1: launch(std::integral_constant<int, 1>(), b, 1); break;
+    case 2: launch(std::integral_constant<int, 2>(), b, 1); break;
+    case 3: launch(std::integral_constant<int, (3 < FTMAX ? 3 : FTMAX)>(), b, 1); break;
+    case 4: launch(std::integral_constant<int, (4 < FTMAX ? 4 : FTMAX)>(), b, 1); break;
+    case 5: launch(std::integral_constant<int, (5 < FTMAX ? 5 : FTMAX)>(), b, 1); break;
+    case 6: launch(std::integral_constant<int, (6 < FTMAX ? 6 : FTMAX)>(), b, 1); break;
+    case 7: launch(std::integral_constant<int, (7 < FTMAX ? 7 : FTMAX)>(), b, 1); break;
+    default: launch(std::integral_constant<int, FTMAX>(), b, 1); break;
+  }
+}
+
 hipError_t launch_nyquist(const srp_geometry_s* g, const void* xi, int F, int dtype, float* map,
                           unsigned long long* keys, hipStream_t s) {
   NyqArgs a;
@@ -624,6 +657,7 @@ hipError_t launch_nyquist(const srp_geometry_s* g, const void* xi, int F, int dt
   a.n_runs = static_cast<int>(g->nyq_runs.size());
   a.xi = static_cast<const float*>(xi);
   a.F = F;
+  a.f_base = 0;
   a.S = static_cast<int>(g->info.S);
   a.J = g->info.J;
   a.inv_cT = g->inv_cT;
@@ -631,32 +665,35 @@ hipError_t launch_nyquist(const srp_geometry_s* g, const void* xi, int F, int dt
   a.map = map;
   a.keys = keys;
   if (dtype == SRP_FP32) {
-    constexpr int FT = 4, FB = 32 * FT;
     int64_t samples = 0;
     for (const PairDesc& pd : g->pairs) samples += 2 * pd.h + 1;
-    if (samples <= kNyqPlainSumMax) {
-      constexpr int CT = 2, JB = 4 * 32 * CT;
-      dim3 grid(static_cast<unsigned>((a.J + JB - 1) / JB), (F + FB - 1) / FB);
-      hipLaunchKernelGGL((nyquist_f32_kernel<CT, FT, false>), grid, dim3(256), 0, s, a, a.mic,
-                         a.pairs, a.runs);
-    } else {
-      constexpr int CT = 1, JB = 4 * 32 * CT;
-      dim3 grid(static_cast<unsigned>((a.J + JB - 1) / JB), (F + FB - 1) / FB);
-      hipLaunchKernelGGL((nyquist_f32_kernel<CT, FT, true>), grid, dim3(256), 0, s, a, a.mic,
-                         a.pairs, a.runs);
-    }
+    if (samples <= kNyqPlainSumMax)
+      launch_frame_blocks<4>(F, a, [&](auto ft, const NyqArgs& b, int fblocks) {
+        constexpr int CT = 2, JB = 4 * 32 * CT;
+        const dim3 grid(static_cast<unsigned>((b.J + JB - 1) / JB), fblocks);
+        hipLaunchKernelGGL((nyquist_f32_kernel<CT, decltype(ft)::value, false>), grid, dim3(256),
+                           0, s, b, b.mic, b.pairs, b.runs);
+      });
+    else
+      launch_frame_blocks<4>(F, a, [&](auto ft, const NyqArgs& b, int fblocks) {
+        constexpr int CT = 1, JB = 4 * 32 * CT;
+        const dim3 grid(static_cast<unsigned>((b.J + JB - 1) / JB), fblocks);
+        hipLaunchKernelGGL((nyquist_f32_kernel<CT, decltype(ft)::value, true>), grid, dim3(256),
+                           0, s, b, b.mic, b.pairs, b.runs);
+      });
     return hipGetLastError();
   }
   if (dtype == SRP_BF16 || dtype == SRP_FP16) {
-    constexpr int FT = 8;
-    constexpr int JB = 4 * 32, FB = 32 * FT;
-    dim3 grid(static_cast<unsigned>((a.J + JB - 1) / JB), (F + FB - 1) / FB);
-    if (dtype == SRP_BF16)
-      hipLaunchKernelGGL((nyquist_mx_kernel<__bf16, FT>), grid, dim3(256), 0, s, a,
-                         static_cast<const __bf16*>(xi), a.mic, a.pairs, a.runs);
-    else
-      hipLaunchKernelGGL((nyquist_mx_kernel<_Float16, FT>), grid, dim3(256), 0, s, a,
-                         static_cast<const _Float16*>(xi), a.mic, a.pairs, a.runs);
+    launch_frame_blocks<8>(F, a, [&](auto ft, const NyqArgs& b, int fblocks) {
+      constexpr int JB = 4 * 32;
+      const dim3 grid(static_cast<unsigned>((b.J + JB - 1) / JB), fblocks);
+      if (dtype == SRP_BF16)
+        hipLaunchKernelGGL((nyquist_mx_kernel<__bf16, decltype(ft)::value>), grid, dim3(256), 0, s,
+                           b, static_cast<const __bf16*>(xi), b.mic, b.pairs, b.runs);
+      else
+        hipLaunchKernelGGL((nyquist_mx_kernel<_Float16, decltype(ft)::value>), grid, dim3(256), 0,
+                           s, b, static_cast<const _Float16*>(xi), b.mic, b.pairs, b.runs);
+    });
     return hipGetLastError();
   }
   if (dtype == SRP_FP64) {
