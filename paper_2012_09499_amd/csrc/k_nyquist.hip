@@ -54,6 +54,7 @@ struct NyqArgs {
   int64_t J;
   double inv_cT;
   int far_field;
+  const float* zero;       // >= 16 zero bytes (staging source past a run's end)
   float* map;              // [F][J] or null
   unsigned long long* keys;  // peaks viewed as u64 pairs, or null
 };
@@ -346,8 +347,11 @@ void nyquist_f32_kernel(NyqArgs a, const double* __restrict__ mic,
 // reciprocal: with r = 1 / (d_j d_{j+1}),  1/d_j = d_{j+1} r  and
 // 1/d_{j+1} = d_j r. The samples are copied to LDS in 16-byte chunks (the
 // sample layout aligns each pair window to 8 samples); chunk c of row r is
-// stored at chunk c ^ (r & 7), so the 8 rows that one 128-byte LDS cycle
-// serves hit 8 different chunks.
+// stored at chunk c ^ ((r >> 1) & 7). The LDS serves 16 lanes x 16 bytes per
+// cycle over 256 bytes of banks, i.e. two 128-byte rows: rows of equal parity
+// share bank halves, and the swizzle gives the 8 rows of each parity among 16
+// consecutive rows 8 different chunks (measured: 187 B/clk per CU for this read
+// pattern, as for a linear read, against 111 B/clk with c ^ (r & 7)).
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
@@ -370,36 +374,40 @@ constexpr int kRowH = kNyqRunMax;  // elements per LDS row (64 lags, 128 bytes)
 
 // Copies one lag run into the swizzled tile [FB][64]: each instruction moves
 // 8 rows (64 lanes x 16 bytes); wave w handles rows 8w, 8w + 32, ...
-template <typename T, int FB>
-__device__ __forceinline__ void stage_run_mx(const T* __restrict__ xi, int S, int F, int f0,
-                                             int nrows, const LagRun& run, int off, T* tile,
-                                             int wave, int lane) {
+template <typename T, int FB, int NW>
+__device__ __forceinline__ void stage_run_mx(const T* __restrict__ xi, const float* zero, int S,
+                                             int F, int f0, int nrows, const RunRec& run,
+                                             T* tile, int wave, int lane) {
   typedef __attribute__((address_space(3))) void* lds_ptr;
+  const int off = run.off;
   if (run.len <= 0) return;
   const int nch = (run.len + 7) >> 3;            // 16-byte chunks holding the run
   const int rsub = lane >> 3;                    // row within the 8-row group
   const int cp = lane & 7;                       // physical chunk in LDS
-  for (int rb = 8 * wave; rb < nrows; rb += 32) {
+  for (int rb = 8 * wave; rb < nrows; rb += 8 * NW) {
     const int row = rb + rsub;
-    const int c = cp ^ (row & 7);                // logical chunk stored at cp
-    const int cc = c < nch ? c : nch - 1;
+    const int c = cp ^ ((row >> 1) & 7);         // logical chunk stored at cp
     const int rr = row < nrows ? row : nrows - 1;
-    const T* src = xi + (size_t)(f0 + rr) * S + off + run.t0 + 8 * cc;
+    // chunks past the run hold zeros, so lags past the run need no weight mask
+    // (a run's last chunk ends at a window end, whose padding is zero)
+    const void* src = c < nch
+        ? static_cast<const void*>(xi + (size_t)(f0 + rr) * S + off + run.t0 + 8 * c)
+        : static_cast<const void*>(zero);
     __builtin_amdgcn_global_load_lds(src, (lds_ptr)(tile + rb * kRowH), 16, 0, 0);
   }
 }
 
 template <typename T, int FT>
-__device__ __forceinline__ void nyq_run_mx(const NyqArgs& a, const double* __restrict__ mic,
-                                           const LagRun& run, const PairDesc& pd,
+__device__ __forceinline__ void nyq_run_mx(const NyqArgs& a, const RunRec& run,
                                            LaneState<1>& st, const T* tile, int cl, int g,
                                            floatx16 (&acc)[FT]) {
   typedef typename MxVec<T>::type vec8;
   if (run.len <= 0) return;
+  const RunRec& pd = run;
   if (run.p != st.cur_p) {
     st.cur_p = run.p;
-    const double* pm = mic + 3 * pd.m;
-    const double* pn = mic + 3 * pd.mp;
+    const double* pm = run.pm;
+    const double* pn = run.pn;
     const bool new_m = pd.m != st.cur_m;
     st.cur_m = pd.m;
     double x;
@@ -423,15 +431,20 @@ __device__ __forceinline__ void nyq_run_mx(const NyqArgs& a, const double* __res
   const int ia = st.xr[0] + pd.h - run.t0 - 8 * g;
   const float qs = (ia & 1) ? -st.sp[0] : st.sp[0];
   const float xf = st.xf[0];
-  float base = static_cast<float>(ia);
   const int steps = (run.len + 15) >> 4;
-  const int rowsw = cl & 7;
-  for (int s = 0; s < steps; ++s, base -= 16.0f) {
-    vec8 av[FT];
-    const int pc = (2 * s + g) ^ rowsw;
+  const int rowsw = (cl >> 1) & 7;
+  const T* trow = tile + cl * kRowH;
+  // software pipeline with ping-pong operand sets: the LDS samples and the
+  // weights of the next step are fetched and formed while the matrix cores
+  // work on the current one (steps past the run re-read its last step and are
+  // never contracted)
+  auto fetch = [&](int s, vec8 (&av)[FT], vec8& wv) {
+    const int sc = s < steps ? s : steps - 1;
+    const int pc = (2 * sc + g) ^ rowsw;
 #pragma unroll
     for (int ft = 0; ft < FT; ++ft)
-      av[ft] = *reinterpret_cast<const vec8*>(tile + (ft * 32 + cl) * kRowH + 8 * pc);
+      av[ft] = *reinterpret_cast<const vec8*>(trow + ft * 32 * kRowH + 8 * pc);
+    const float base = static_cast<float>(ia - 16 * s);
     float w[8];
 #pragma unroll
     for (int j = 0; j < 8; j += 2) {
@@ -441,24 +454,49 @@ __device__ __forceinline__ void nyq_run_mx(const NyqArgs& a, const double* __res
       w[j] = qr * d1;
       w[j + 1] = -qr * d0;
     }
-    if (16 * s + 16 > run.len) {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) w[j] = 16 * s + 8 * g + j < run.len ? w[j] : 0.0f;
-    }
-    vec8 wv;
 #pragma unroll
     for (int j = 0; j < 8; ++j) wv[j] = static_cast<T>(w[j]);
+  };
+  auto contract = [&](const vec8 (&av)[FT], const vec8& wv) {
 #pragma unroll
     for (int ft = 0; ft < FT; ++ft) acc[ft] = MxVec<T>::mfma(av[ft], wv, acc[ft]);
+  };
+  auto order = [&]() {
+    // issue order: one matrix-core instruction, the next step's LDS reads,
+    // then the weight arithmetic slotted between the remaining instructions
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x100, FT, 0);
+#pragma unroll
+    for (int i = 1; i < FT; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    }
+  };
+  vec8 a0[FT], a1[FT], w0, w1;
+  fetch(0, a0, w0);
+  int s = 0;
+  for (; s + 1 < steps; s += 2) {
+    fetch(s + 1, a1, w1);
+    contract(a0, w0);
+    order();
+    fetch(s + 2, a0, w0);
+    contract(a1, w1);
+    order();
   }
+  if (s < steps) contract(a0, w0);
 }
 
+// Waves per workgroup of the BF16/FP16 kernel: every wave of the workgroup
+// uses each staged lag run, so more waves mean fewer copies of the samples
+// per candidate (the copies, not the matrix cores, bound this kernel).
+constexpr int kMxWaves = 8;
+
 template <typename T, int FT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
-void nyquist_mx_kernel(NyqArgs a, const T* __restrict__ xi, const double* __restrict__ mic,
-                       const PairDesc* __restrict__ pairs, const LagRun* __restrict__ runs) {
+__global__ __launch_bounds__(64 * kMxWaves) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void nyquist_mx_kernel(NyqArgs a, const T* __restrict__ xi, const RunRec* __restrict__ recs) {
+  constexpr int NW = kMxWaves;
   constexpr int FB = 32 * FT;
-  constexpr int JB = 4 * 32;
+  constexpr int JB = NW * 32;
   __shared__ __attribute__((aligned(16))) T xs0[FB * kRowH];
   __shared__ __attribute__((aligned(16))) T xs1[FB * kRowH];
   __shared__ unsigned long long kbest[FB];
@@ -486,7 +524,7 @@ void nyquist_mx_kernel(NyqArgs a, const T* __restrict__ xi, const double* __rest
   }
   st.cur_m = -1;
   st.cur_p = -1;
-  for (int i = tid; i < FB; i += 256) kbest[i] = 0ull;
+  for (int i = tid; i < FB; i += 64 * NW) kbest[i] = 0ull;
 
   floatx16 acc[FT];
 #pragma unroll
@@ -494,33 +532,21 @@ void nyquist_mx_kernel(NyqArgs a, const T* __restrict__ xi, const double* __rest
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[ft][r] = 0.0f;
 
-  {
-    const LagRun r0 = runs[0];
-    stage_run_mx<T, FB>(xi, a.S, a.F, f0, nrows, r0, pairs[r0.p].off, xs0, wave, lane);
-  }
+  stage_run_mx<T, FB, NW>(xi, a.zero, a.S, a.F, f0, nrows, recs[0], xs0, wave, lane);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   for (int ri = 0; ri < a.n_runs; ri += 2) {
-    {
-      const LagRun run = runs[ri];
-      const PairDesc pd = pairs[run.p];
-      const LagRun nx = runs[ri + 1];
-      stage_run_mx<T, FB>(xi, a.S, a.F, f0, nrows, nx, pairs[nx.p].off, xs1, wave, lane);
-      nyq_run_mx<T, FT>(a, mic, run, pd, st, xs0, cl, g, acc);
-      __builtin_amdgcn_s_waitcnt(0);
-      __syncthreads();
-    }
-    {
-      const LagRun run = runs[ri + 1];
-      const PairDesc pd = pairs[run.p];
-      if (ri + 2 < a.n_runs) {
-        const LagRun nx = runs[ri + 2];
-        stage_run_mx<T, FB>(xi, a.S, a.F, f0, nrows, nx, pairs[nx.p].off, xs0, wave, lane);
-      }
-      nyq_run_mx<T, FT>(a, mic, run, pd, st, xs1, cl, g, acc);
-      __builtin_amdgcn_s_waitcnt(0);
-      __syncthreads();
-    }
+    const RunRec r0 = recs[ri];
+    const RunRec r1 = recs[ri + 1];
+    stage_run_mx<T, FB, NW>(xi, a.zero, a.S, a.F, f0, nrows, r1, xs1, wave, lane);
+    nyq_run_mx<T, FT>(a, r0, st, xs0, cl, g, acc);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (ri + 2 < a.n_runs)
+      stage_run_mx<T, FB, NW>(xi, a.zero, a.S, a.F, f0, nrows, recs[ri + 2], xs0, wave, lane);
+    nyq_run_mx<T, FT>(a, r1, st, xs1, cl, g, acc);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
   }
 
   const int64_t ci = jb + cl;
@@ -544,7 +570,7 @@ void nyquist_mx_kernel(NyqArgs a, const T* __restrict__ xi, const double* __rest
   }
   if (a.keys) {
     __syncthreads();
-    for (int i = tid; i < FB; i += 256) {
+    for (int i = tid; i < FB; i += 64 * NW) {
       const unsigned long long k = kbest[i];
       if (k && f0 + i < a.F) atomicMax(a.keys + 2 * (size_t)(f0 + i), k);
     }
@@ -664,6 +690,7 @@ hipError_t launch_nyquist(const srp_geometry_s* g, const void* xi, int F, int dt
   a.far_field = g->info.field == SRP_FAR_FIELD;
   a.map = map;
   a.keys = keys;
+  a.zero = g->d_zero;
   if (dtype == SRP_FP32) {
     int64_t samples = 0;
     for (const PairDesc& pd : g->pairs) samples += 2 * pd.h + 1;
@@ -685,14 +712,14 @@ hipError_t launch_nyquist(const srp_geometry_s* g, const void* xi, int F, int dt
   }
   if (dtype == SRP_BF16 || dtype == SRP_FP16) {
     launch_frame_blocks<8>(F, a, [&](auto ft, const NyqArgs& b, int fblocks) {
-      constexpr int JB = 4 * 32;
-      const dim3 grid(static_cast<unsigned>((b.J + JB - 1) / JB), fblocks);
+      constexpr int JB = kMxWaves * 32;
+      const dim3 grid(static_cast<unsigned>((b.J + JB - 1) / JB), fblocks), blk(64 * kMxWaves);
       if (dtype == SRP_BF16)
-        hipLaunchKernelGGL((nyquist_mx_kernel<__bf16, decltype(ft)::value>), grid, dim3(256), 0, s,
-                           b, static_cast<const __bf16*>(xi), b.mic, b.pairs, b.runs);
+        hipLaunchKernelGGL((nyquist_mx_kernel<__bf16, decltype(ft)::value>), grid, blk, 0, s, b,
+                           static_cast<const __bf16*>(xi), g->d_nyq_recs);
       else
-        hipLaunchKernelGGL((nyquist_mx_kernel<_Float16, decltype(ft)::value>), grid, dim3(256), 0,
-                           s, b, static_cast<const _Float16*>(xi), b.mic, b.pairs, b.runs);
+        hipLaunchKernelGGL((nyquist_mx_kernel<_Float16, decltype(ft)::value>), grid, blk, 0, s, b,
+                           static_cast<const _Float16*>(xi), g->d_nyq_recs);
     });
     return hipGetLastError();
   }

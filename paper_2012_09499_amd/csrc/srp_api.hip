@@ -101,11 +101,13 @@ void free_geometry(srp_geometry_s* g) {
   hipFree(g->d_pairs);
   hipFree(g->d_gcc_tiles);
   hipFree(g->d_nyq_runs);
+  hipFree(g->d_nyq_recs);
   hipFree(g->d_conv_runs);
   hipFree(g->d_window);
   hipFree(g->d_twiddle);
   hipFree(g->d_gcc_table);
   hipFree(g->d_binw);
+  hipFree(g->d_zero);
   delete g;
 }
 
@@ -269,11 +271,32 @@ srp_status srp_geometry(const double* mic_xyz, int32_t M, const double* cand_xyz
   if (e == hipSuccess) e = upload(&g->d_pairs, g->pairs.data(), g->pairs.size(), s);
   if (e == hipSuccess) e = upload(&g->d_gcc_tiles, g->gcc_tiles.data(), g->gcc_tiles.size(), s);
   if (e == hipSuccess) e = upload(&g->d_nyq_runs, g->nyq_runs.data(), g->nyq_runs.size(), s);
+  std::vector<RunRec> recs(g->nyq_runs.size());
+  for (size_t i = 0; i < recs.size(); ++i) {
+    const LagRun& r = g->nyq_runs[i];
+    const PairDesc& pd = g->pairs[r.p];
+    RunRec& q = recs[i];
+    q.p = r.p;
+    q.t0 = r.t0;
+    q.len = r.len;
+    q.off = pd.off;
+    q.h = pd.h;
+    q.m = pd.m;
+    q.mp = pd.mp;
+    q.pad = 0;
+    for (int d = 0; d < 3; ++d) {
+      q.pm[d] = mic_xyz[3 * pd.m + d];
+      q.pn[d] = mic_xyz[3 * pd.mp + d];
+    }
+  }
+  if (e == hipSuccess) e = upload(&g->d_nyq_recs, recs.data(), recs.size(), s);
   if (e == hipSuccess) e = upload(&g->d_conv_runs, g->conv_runs.data(), g->conv_runs.size(), s);
   if (e == hipSuccess) e = upload(&g->d_window, win.data(), win.size(), s);
   if (e == hipSuccess) e = upload(&g->d_twiddle, tw.data(), tw.size(), s);
   if (e == hipSuccess) e = upload(&g->d_gcc_table, gtab.data(), gtab.size(), s);
   if (e == hipSuccess) e = upload(&g->d_binw, binw.data(), binw.size(), s);
+  const std::vector<float> zeros(64, 0.0f);
+  if (e == hipSuccess) e = upload(&g->d_zero, zeros.data(), zeros.size(), s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     const bool oom = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation);

@@ -25,6 +25,15 @@ struct LagRun {
   int32_t p, t0, len, pad;
 };
 
+// Everything the BF16/FP16 interpolation kernel needs for one lag run in one
+// record, so a run costs one scalar load instead of the dependent chain
+// run -> pair -> microphone positions.
+struct RunRec {
+  int32_t p, t0, len, off;  // the run, and its pair's window offset in the sample layout
+  int32_t h, m, mp, pad;    // the pair: half window, microphones m > mp
+  double pm[3], pn[3];      // positions of microphones m and mp
+};
+
 // Lag runs of the Nyquist interpolation kernels are at most this long (one
 // lane per lag when a wave copies a run into LDS).
 constexpr int kNyqRunMax = 64;
@@ -80,11 +89,13 @@ struct srp_geometry_s {
   srp::PairDesc* d_pairs = nullptr;    // [P]
   srp::LagRun* d_gcc_tiles = nullptr;
   srp::LagRun* d_nyq_runs = nullptr;
+  srp::RunRec* d_nyq_recs = nullptr;   // one record per entry of nyq_runs
   srp::LagRun* d_conv_runs = nullptr;
   float* d_window = nullptr;           // [L]
   float2* d_twiddle = nullptr;         // [L/2] exp(-j 2 pi t / L)
   float2* d_gcc_table = nullptr;       // [K][gcc_nw] (cos, -sin) of 2 pi f_k n T
   float* d_binw = nullptr;             // [K]
+  float* d_zero = nullptr;             // 64 zeros (source of zero-filled staging chunks)
 };
 
 namespace srp {
