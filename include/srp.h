@@ -175,6 +175,48 @@ srp_status srp_map_conventional(const srp_geometry_t* g, const float* psi, int32
 srp_status srp_map_nyquist(const srp_geometry_t* g, const void* xi, int32_t F, int32_t dtype,
                            float* map, srp_peak* peaks, void* stream);
 
+/* Cached interpolation weights (Section 3.3: the weights sinc(dt_p(i)/T - n)
+ * of Eq. SRPapprox do not depend on the frames; cost of the map with them,
+ * Eq. SRPapproxcompR). The weight matrix W is J x Sw, row-major (one row per
+ * candidate), Sw = S rounded up to a multiple of 128, in the column layout of
+ * the GCC samples: W[i][off_p + n + h_p] = sinc(dt_p(i)/T - n) for |n| <= h_p,
+ * 0 in the gap columns and past S. Every entry is computed in float64 and
+ * rounded once to bfloat16 (SRP_BF16) or half (SRP_FP16). The caller owns the
+ * buffer (J * Sw * 2 bytes; e.g. 8.1 GB for 576,000 candidates and S = 7,008)
+ * and decides whether the geometry is worth caching.
+ *   srp_nyquist_weights_bytes  size of W for dtype; SRP_ERR_UNSUPPORTED for
+ *                              any dtype other than SRP_BF16 / SRP_FP16
+ *   srp_nyquist_weights        writes W (device, 16-byte aligned, >= bytes) */
+srp_status srp_nyquist_weights_bytes(const srp_geometry_t* g, int32_t dtype, size_t* bytes);
+srp_status srp_nyquist_weights(const srp_geometry_t* g, int32_t dtype, void* weights,
+                               size_t bytes, void* stream);
+
+/* Nyquist map from cached weights: map[f][i] = 2 sum_k W[i][k] xi[f][k] over
+ * the packed columns (the same sum as srp_map_nyquist, Eq. SRPapprox summed
+ * over pairs as in Eq. SRP_T_IFT, with the weights read instead of formed).
+ *   weights  device, written by srp_nyquist_weights for this geometry and dtype
+ *   xi       device, F x S samples written by srp_gcc_samples with this dtype
+ *            (16-byte aligned)
+ *   dtype    SRP_BF16 or SRP_FP16 (matrix cores, float32 accumulation)
+ *   map, peaks as for srp_map_nyquist */
+srp_status srp_map_nyquist_cached(const srp_geometry_t* g, const void* weights, const void* xi,
+                                  int32_t F, int32_t dtype, float* map, srp_peak* peaks,
+                                  void* stream);
+
+/* Nyquist SRP at arbitrary points, different for every frame (Eq. SRPapprox
+ * summed over pairs as in Eq. SRP_T_IFT): the interpolation defines the map
+ * off the candidate grid too, so a coarse map's peak can be refined on finer
+ * local grids from the same samples (the refined spatial search that Section 1
+ * and Section 3.3 name as an extension; the package's refine_peaks does this).
+ *   xi      device, F x S float32 samples (srp_gcc_samples, SRP_FP32)
+ *   points  device, F x Q x 3 float64: positions in metres (near field) or
+ *           unit propagation directions (far field; not checked), per frame
+ *   values  device, F x Q float32, written: 2 sum_p xi_p,appr(dt_p(point))
+ * float32 vector arithmetic with the float64 TDOA split of srp_map_nyquist;
+ * 1 <= F <= 65535, Q >= 1. */
+srp_status srp_map_nyquist_points(const srp_geometry_t* g, const float* xi, int32_t F,
+                                  const double* points, int32_t Q, float* values, void* stream);
+
 /* One item of a batched Nyquist launch: an array and its frames of the batch. */
 typedef struct {
   const srp_geometry_t* g;   /* the array                                            */

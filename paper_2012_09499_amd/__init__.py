@@ -7,6 +7,8 @@ pipeline helper.
 """
 from ._lib import (DTYPES, EXPORTS, Geometry, SrpError, argmax, cross_spectra, decode_peaks,  # noqa: F401
                    batched_workspace_bytes, gcc_samples, lib, map_conventional, map_nyquist,
-                   map_nyquist_batched, pair_layout, sample_torch_dtype, unpack_samples,
+                   map_nyquist_batched, map_nyquist_cached, map_nyquist_points, nyquist_weights,
+                   nyquist_weights_bytes, pair_layout, sample_torch_dtype, unpack_samples,
                    version)
 from .pipeline import SrpPipeline  # noqa: F401
+from .refine import refine_peaks  # noqa: F401

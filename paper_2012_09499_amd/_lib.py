@@ -32,7 +32,9 @@ PHAT = 0
 EXPORTS = ("srp_pair_layout", "srp_geometry", "srp_geometry_query", "srp_geometry_destroy",
            "srp_cross_spectra_workspace", "srp_cross_spectra", "srp_gcc_samples",
            "srp_map_conventional", "srp_map_nyquist", "srp_map_nyquist_batched_workspace",
-           "srp_map_nyquist_batched", "srp_argmax", "srp_last_error", "srp_version")
+           "srp_map_nyquist_batched", "srp_nyquist_weights_bytes", "srp_nyquist_weights",
+           "srp_map_nyquist_cached", "srp_map_nyquist_points", "srp_argmax", "srp_last_error",
+           "srp_version")
 BATCH_MAX_F = 8            # frames per item of a batched launch, FP32 samples
 BATCH_MAX_F_MX = 16        # ... BF16 / FP16 samples (matrix-core tile)
 
@@ -86,6 +88,10 @@ def lib() -> C.CDLL:
     L.srp_argmax.argtypes = [vp, i32, i64, vp, vp]
     L.srp_map_nyquist_batched_workspace.argtypes = [i32, C.POINTER(C.c_size_t)]
     L.srp_map_nyquist_batched.argtypes = [vp, i32, vp, i32, vp, C.c_size_t, vp]
+    L.srp_nyquist_weights_bytes.argtypes = [vp, i32, C.POINTER(C.c_size_t)]
+    L.srp_nyquist_weights.argtypes = [vp, i32, vp, C.c_size_t, vp]
+    L.srp_map_nyquist_cached.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp]
+    L.srp_map_nyquist_points.argtypes = [vp, vp, i32, vp, i32, vp, vp]
     L.srp_last_error.restype = C.c_char_p
     L.srp_last_error.argtypes = []
     L.srp_version.restype = C.c_char_p
@@ -278,6 +284,74 @@ def map_conventional(g: Geometry, psi, dtype: str = "fp32", want_map: bool = Tru
                                       pk.data_ptr() if pk is not None else None,
                                       _stream_handle(stream)))
     return m, pk
+
+
+def nyquist_weights_bytes(g: Geometry, dtype: str = "bf16") -> int:
+    """Bytes of the cached weight matrix W [J][Sw] (srp_nyquist_weights_bytes)."""
+    n = C.c_size_t(0)
+    _check(lib().srp_nyquist_weights_bytes(g.handle, DTYPES[dtype], C.byref(n)))
+    return int(n.value)
+
+
+def nyquist_weights(g: Geometry, dtype: str = "bf16", out=None, stream=None):
+    """Builds the float64-exact, once-rounded weight matrix W [J][Sw] (srp_nyquist_weights)."""
+    import torch
+    nbytes = nyquist_weights_bytes(g, dtype)
+    cols = nbytes // (2 * g.J)
+    tdt = sample_torch_dtype(dtype)
+    if out is None:
+        out = torch.empty((g.J, cols), dtype=tdt, device="cuda")
+    _need_cuda(out, "weights", tdt, (g.J, cols))
+    _check(lib().srp_nyquist_weights(g.handle, DTYPES[dtype], out.data_ptr(), nbytes,
+                                     _stream_handle(stream)))
+    return out
+
+
+def map_nyquist_cached(g: Geometry, weights, xi, dtype: str = "bf16", want_map: bool = True,
+                       want_peaks: bool = True, map_out=None, peaks_out=None, stream=None):
+    """xi [F][S] + cached W -> (map [F][J] | None, peaks [F][2] | None) (srp_map_nyquist_cached)."""
+    import torch
+    tdt = sample_torch_dtype(dtype)
+    _need_cuda(xi, "xi", tdt)
+    _need_cuda(weights, "weights", tdt)
+    F = xi.shape[0]
+    if tuple(xi.shape) != (F, g.S):
+        raise ValueError(f"xi must have shape (F, {g.S})")
+    if weights.shape[0] != g.J or weights.numel() * 2 < nyquist_weights_bytes(g, dtype):
+        raise ValueError("weights do not match this geometry")
+    m = map_out if map_out is not None else (
+        torch.empty((F, g.J), dtype=torch.float32, device=xi.device) if want_map else None)
+    pk = peaks_out if peaks_out is not None else (
+        torch.empty((F, 2), dtype=torch.int64, device=xi.device) if want_peaks else None)
+    if m is not None:
+        _need_cuda(m, "map", torch.float32, (F, g.J))
+    if pk is not None:
+        _need_cuda(pk, "peaks", torch.int64, (F, 2))
+    _check(lib().srp_map_nyquist_cached(g.handle, weights.data_ptr(), xi.data_ptr(), F,
+                                        DTYPES[dtype], m.data_ptr() if m is not None else None,
+                                        pk.data_ptr() if pk is not None else None,
+                                        _stream_handle(stream)))
+    return m, pk
+
+
+def map_nyquist_points(g: Geometry, xi, points, out=None, stream=None):
+    """xi [F][S] float32, points [F][Q][3] float64 (CUDA) -> values [F][Q] float32
+    (srp_map_nyquist_points)."""
+    import torch
+    _need_cuda(xi, "xi", torch.float32)
+    F = xi.shape[0]
+    if tuple(xi.shape) != (F, g.S):
+        raise ValueError(f"xi must have shape (F, {g.S})")
+    _need_cuda(points, "points", torch.float64)
+    if points.dim() != 3 or points.shape[0] != F or points.shape[2] != 3:
+        raise ValueError("points must have shape (F, Q, 3)")
+    Q = points.shape[1]
+    if out is None:
+        out = torch.empty((F, Q), dtype=torch.float32, device=xi.device)
+    _need_cuda(out, "values", torch.float32, (F, Q))
+    _check(lib().srp_map_nyquist_points(g.handle, xi.data_ptr(), F, points.data_ptr(), Q,
+                                        out.data_ptr(), _stream_handle(stream)))
+    return out
 
 
 def batched_workspace_bytes(n_items: int) -> int:

@@ -21,7 +21,7 @@ LIB = os.path.join(PKG, "libsrp.so")
 ARCH = "gfx950"
 
 SOURCES = ["srp_api.hip", "k_spectra.hip", "k_gcc.hip", "k_nyquist.hip", "k_conventional.hip",
-           "k_argmax.hip", "k_batched.hip"]
+           "k_argmax.hip", "k_batched.hip", "k_cached.hip", "k_points.hip"]
 
 COMMON = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

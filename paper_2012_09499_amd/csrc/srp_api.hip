@@ -108,6 +108,7 @@ void free_geometry(srp_geometry_s* g) {
   hipFree(g->d_gcc_table);
   hipFree(g->d_binw);
   hipFree(g->d_zero);
+  hipFree(g->d_chunk_pair);
   delete g;
 }
 
@@ -297,6 +298,15 @@ srp_status srp_geometry(const double* mic_xyz, int32_t M, const double* cand_xyz
   if (e == hipSuccess) e = upload(&g->d_binw, binw.data(), binw.size(), s);
   const std::vector<float> zeros(64, 0.0f);
   if (e == hipSuccess) e = upload(&g->d_zero, zeros.data(), zeros.size(), s);
+  // cached-weight columns: the pair owning each 8-column chunk (window plus gap)
+  std::vector<int> chunk_pair((g->info.S + 127) / 128 * 16, -1);
+  for (int p = 0; p < P; ++p) {
+    const int64_t W8 = (2 * (int64_t)g->pairs[p].h + 1 + kSampleAlign - 1) / kSampleAlign *
+                       kSampleAlign;
+    for (int64_t c = g->pairs[p].off; c < g->pairs[p].off + W8; c += 8)
+      chunk_pair[c / 8] = p;
+  }
+  if (e == hipSuccess) e = upload(&g->d_chunk_pair, chunk_pair.data(), chunk_pair.size(), s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     const bool oom = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation);
@@ -390,6 +400,67 @@ srp_status srp_map_nyquist(const srp_geometry_t* g, const void* xi, int32_t F, i
   if (e == hipSuccess && peaks) e = launch_peaks_finalize(peaks, F, s);
   if (e == hipErrorNotSupported) return fail(SRP_ERR_UNSUPPORTED, "dtype not supported here");
   if (e != hipSuccess) return device_fail(e, "map_nyquist");
+  return SRP_OK;
+}
+
+srp_status srp_nyquist_weights_bytes(const srp_geometry_t* g, int32_t dtype, size_t* bytes) {
+  if (g == nullptr || bytes == nullptr) return fail(SRP_ERR_INVALID_ARG, "NULL argument");
+  if (dtype != SRP_BF16 && dtype != SRP_FP16)
+    return fail(SRP_ERR_UNSUPPORTED, "cached weights are BF16 or FP16");
+  *bytes = (size_t)g->info.J * (size_t)cached_weight_cols(g) * 2;
+  return SRP_OK;
+}
+
+srp_status srp_nyquist_weights(const srp_geometry_t* g, int32_t dtype, void* weights,
+                               size_t bytes, void* stream) {
+  size_t need = 0;
+  srp_status st = srp_nyquist_weights_bytes(g, dtype, &need);
+  if (st != SRP_OK) return st;
+  if (weights == nullptr) return fail(SRP_ERR_INVALID_ARG, "weights is NULL");
+  if (bytes < need) return fail(SRP_ERR_INVALID_ARG, "weights buffer too small");
+  if ((reinterpret_cast<uintptr_t>(weights) & 15) != 0)
+    return fail(SRP_ERR_INVALID_ARG, "weights must be 16-byte aligned");
+  DeviceGuard dg(g->device);
+  if (!dg.ok) return fail(SRP_ERR_DEVICE, "cannot select the geometry's device");
+  hipError_t e = launch_nyquist_weights(g, dtype, weights, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return device_fail(e, "nyquist_weights");
+  return SRP_OK;
+}
+
+srp_status srp_map_nyquist_cached(const srp_geometry_t* g, const void* weights, const void* xi,
+                                  int32_t F, int32_t dtype, float* map, srp_peak* peaks,
+                                  void* stream) {
+  srp_status st = check_map_args(g, xi, F, dtype, map, peaks);
+  if (st != SRP_OK) return st;
+  if (dtype != SRP_BF16 && dtype != SRP_FP16)
+    return fail(SRP_ERR_UNSUPPORTED, "cached weights are BF16 or FP16");
+  if (weights == nullptr) return fail(SRP_ERR_INVALID_ARG, "weights is NULL");
+  if ((reinterpret_cast<uintptr_t>(weights) & 15) != 0 ||
+      (reinterpret_cast<uintptr_t>(xi) & 15) != 0)
+    return fail(SRP_ERR_INVALID_ARG, "weights and xi must be 16-byte aligned");
+  DeviceGuard dg(g->device);
+  if (!dg.ok) return fail(SRP_ERR_DEVICE, "cannot select the geometry's device");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipSuccess;
+  if (peaks) e = launch_peaks_init(peaks, F, s);
+  if (e == hipSuccess)
+    e = launch_nyquist_cached(g, weights, xi, F, dtype, map,
+                              reinterpret_cast<unsigned long long*>(peaks), s);
+  if (e == hipSuccess && peaks) e = launch_peaks_finalize(peaks, F, s);
+  if (e != hipSuccess) return device_fail(e, "map_nyquist_cached");
+  return SRP_OK;
+}
+
+srp_status srp_map_nyquist_points(const srp_geometry_t* g, const float* xi, int32_t F,
+                                  const double* points, int32_t Q, float* values, void* stream) {
+  if (g == nullptr || xi == nullptr || points == nullptr || values == nullptr)
+    return fail(SRP_ERR_INVALID_ARG, "NULL argument");
+  if (F < 1 || F > 65535) return fail(SRP_ERR_INVALID_ARG, "F must be in [1, 65535]");
+  if (Q < 1) return fail(SRP_ERR_INVALID_ARG, "Q must be >= 1");
+  DeviceGuard dg(g->device);
+  if (!dg.ok) return fail(SRP_ERR_DEVICE, "cannot select the geometry's device");
+  hipError_t e = launch_points(g, xi, F, points, Q, values, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return device_fail(e, "map_nyquist_points");
   return SRP_OK;
 }
 

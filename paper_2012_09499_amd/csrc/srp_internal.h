@@ -96,6 +96,7 @@ struct srp_geometry_s {
   float2* d_gcc_table = nullptr;       // [K][gcc_nw] (cos, -sin) of 2 pi f_k n T
   float* d_binw = nullptr;             // [K]
   float* d_zero = nullptr;             // 64 zeros (source of zero-filled staging chunks)
+  int* d_chunk_pair = nullptr;         // pair of each 8-column chunk of the cached weights (-1: none)
 };
 
 namespace srp {
@@ -119,6 +120,12 @@ hipError_t launch_conventional(const srp_geometry_s* g, const float2* psi, int F
 hipError_t launch_nyquist_batched(const BatchItemDev* d_items, int n_vec, int blocks_vec,
                                   int max_f_vec, int n_mx, int blocks_mx, int dtype,
                                   const void* xi, hipStream_t s);
+hipError_t launch_points(const srp_geometry_s* g, const float* xi, int F, const double* pts,
+                         int Q, float* out, hipStream_t s);
+int cached_weight_cols(const srp_geometry_s* g);
+hipError_t launch_nyquist_weights(const srp_geometry_s* g, int dtype, void* w, hipStream_t s);
+hipError_t launch_nyquist_cached(const srp_geometry_s* g, const void* w, const void* xi, int F,
+                                 int dtype, float* map, unsigned long long* keys, hipStream_t s);
 hipError_t launch_peaks_init(srp_peak* peaks, int F, hipStream_t s);
 hipError_t launch_peaks_finalize(srp_peak* peaks, int F, hipStream_t s);
 hipError_t launch_argmax(const float* map, int F, int64_t J, unsigned long long* keys,

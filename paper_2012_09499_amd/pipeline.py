@@ -40,10 +40,18 @@ class SrpPipeline:
                                                device=self.device)
         return self._xi_lowp[dtype]
 
-    def nyquist(self, frames, dtype: str = "fp32"):
+    def nyquist(self, frames, dtype: str = "fp32", weights=None):
+        """Nyquist map of a frame batch; with `weights` (from nyquist_weights for
+        this geometry and dtype) the map reads the cached weights instead of
+        forming them."""
         F = frames.shape[0]
         psi = self.spectra(frames)
         xi = S.gcc_samples(self.g, psi, out=self.samples_buffer(dtype)[:F], dtype=dtype)
+        if weights is not None:
+            return S.map_nyquist_cached(self.g, weights, xi, dtype=dtype,
+                                        want_map=self.map is not None,
+                                        map_out=None if self.map is None else self.map[:F],
+                                        peaks_out=self.peaks[:F])
         return S.map_nyquist(self.g, xi, dtype=dtype, want_map=self.map is not None,
                              map_out=None if self.map is None else self.map[:F],
                              peaks_out=self.peaks[:F])
