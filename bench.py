@@ -230,7 +230,8 @@ def main():
     ap.add_argument("--conv-steps", type=int, default=3)
     ap.add_argument("--no-conventional", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-candidates", type=int, default=40000)
+    ap.add_argument("--cpu-candidates", type=int, default=120000,
+                    help="candidates of the oracle's timed sample (about 10 s on 16 threads)")
     ap.add_argument("--serving-seconds", type=float, default=10.0,
                     help="length of the serving run (0 skips it)")
     ap.add_argument("--serving-leg", choices=("fp32", "bf16", "fp16"), default=None,

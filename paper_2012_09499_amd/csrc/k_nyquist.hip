@@ -650,16 +650,18 @@ template <int FTMAX, typename Launch>
 void launch_frame_blocks(int F, const NyqArgs& a, Launch&& launch) {
   constexpr int FB = 32 * FTMAX;
   const int full = F / FB;
-  if (full > 0) {
+  const int rem = F - full * FB;
+  const int tiles = (rem + 31) / 32;  // 0 .. FTMAX (FTMAX <= 8)
+  // a remainder that needs every tile anyway is one more block of the launch
+  const int blocks = full + (tiles == FTMAX ? 1 : 0);
+  if (blocks > 0) {
     NyqArgs b = a;
     b.f_base = 0;
-    launch(std::integral_constant<int, FTMAX>(), b, full);
+    launch(std::integral_constant<int, FTMAX>(), b, blocks);
   }
-  const int rem = F - full * FB;
-  if (rem == 0) return;
+  if (tiles == 0 || tiles == FTMAX) return;
   NyqArgs b = a;
   b.f_base = full * FB;
-  const int tiles = (rem + 31) / 32;  // 1 .. FTMAX (FTMAX <= 8)
   static_assert(FTMAX <= 8, "tail dispatch covers up to 8 tiles");
   switch (tiles) {
     case 1: launch(std::integral_constant<int, 1>(), b, 1); break;
