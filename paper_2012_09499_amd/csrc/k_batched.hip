@@ -50,6 +50,39 @@ __device__ __forceinline__ void load_pair(const _Float16* p, float& a, float& b)
   b = static_cast<float>(__builtin_bit_cast(_Float16, static_cast<unsigned short>(u >> 16)));
 }
 
+// Eight consecutive samples (starting at a multiple of 8 within a window,
+// so 16-bit chunks are 16-byte aligned) as floats; one scalar load when the
+// address is uniform.
+struct F8 {
+  float v[8];
+};
+struct U4 {
+  unsigned u[4];
+};
+__device__ __forceinline__ void load8(const float* p, float (&x)[8]) {
+  const F8 c = *reinterpret_cast<const F8*>(p);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) x[j] = c.v[j];
+}
+__device__ __forceinline__ void load8(const __bf16* p, float (&x)[8]) {
+  const U4 c = *reinterpret_cast<const U4*>(p);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    x[2 * j] = __uint_as_float(c.u[j] << 16);
+    x[2 * j + 1] = __uint_as_float(c.u[j] & 0xffff0000u);
+  }
+}
+__device__ __forceinline__ void load8(const _Float16* p, float (&x)[8]) {
+  const U4 c = *reinterpret_cast<const U4*>(p);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    x[2 * j] = static_cast<float>(
+        __builtin_bit_cast(_Float16, static_cast<unsigned short>(c.u[j] & 0xffffu)));
+    x[2 * j + 1] = static_cast<float>(
+        __builtin_bit_cast(_Float16, static_cast<unsigned short>(c.u[j] >> 16)));
+  }
+}
+
 template <int FMAX, typename T>
 __global__ __launch_bounds__(256) void nyquist_batched_kernel(const BatchItemDev* __restrict__ items,
                                                                int n_items,
@@ -103,11 +136,35 @@ __global__ __launch_bounds__(256) void nyquist_batched_kernel(const BatchItemDev
     float acc[FMAX];
 #pragma unroll
     for (int f = 0; f < FMAX; ++f) acc[f] = 0.0f;
-    const T* col = xi + it.xi_off + pd.off;
+    // rows of frames past the item's F repeat its last frame (branch-free;
+    // their sums are discarded)
+    const T* row[FMAX];
+#pragma unroll
+    for (int f = 0; f < FMAX; ++f)
+      row[f] = xi + it.xi_off + (size_t)(f < it.F ? f : it.F - 1) * it.S + pd.off;
     const int W = 2 * pd.h + 1;
     float base = static_cast<float>(ia);
     int t = 0;
-#pragma unroll 4
+    // 8 lags per iteration: each frame's 8 samples arrive by one scalar load,
+    // issued together before the arithmetic that uses them
+    for (; t + 8 <= W; t += 8) {
+      float xs[FMAX][8];
+#pragma unroll
+      for (int f = 0; f < FMAX; ++f) load8(row[f] + t, xs[f]);
+#pragma unroll
+      for (int j = 0; j < 8; j += 2, base -= 2.0f) {
+        const float d0 = base + xf;
+        const float d1 = (base - 1.0f) + xf;
+        const float qr = q0 * __builtin_amdgcn_rcpf(d0 * d1);
+        const float w0 = qr * d1;
+        const float w1 = -qr * d0;
+#pragma unroll
+        for (int f = 0; f < FMAX; ++f) {
+          acc[f] = fmaf(w0, xs[f][j], acc[f]);
+          acc[f] = fmaf(w1, xs[f][j + 1], acc[f]);
+        }
+      }
+    }
     for (; t + 1 < W; t += 2, base -= 2.0f) {
       const float d0 = base + xf;
       const float d1 = (base - 1.0f) + xf;
@@ -116,23 +173,19 @@ __global__ __launch_bounds__(256) void nyquist_batched_kernel(const BatchItemDev
       const float w1 = -qr * d0;
 #pragma unroll
       for (int f = 0; f < FMAX; ++f) {
-        if (f < it.F) {
-          float x0, x1;
-          load_pair(col + (size_t)f * it.S + t, x0, x1);
-          acc[f] = fmaf(w0, x0, acc[f]);
-          acc[f] = fmaf(w1, x1, acc[f]);
-        }
+        float x0, x1;
+        load_pair(row[f] + t, x0, x1);
+        acc[f] = fmaf(w0, x0, acc[f]);
+        acc[f] = fmaf(w1, x1, acc[f]);
       }
     }
     {  // last lag (W is odd)
       const float w0 = q0 * __builtin_amdgcn_rcpf(base + xf);
 #pragma unroll
       for (int f = 0; f < FMAX; ++f) {
-        if (f < it.F) {
-          float x0, x1;  // x1 is the first zero of the window's padding
-          load_pair(col + (size_t)f * it.S + t, x0, x1);
-          acc[f] = fmaf(w0, x0, acc[f]);
-        }
+        float x0, x1;  // x1 is the first zero of the window's padding
+        load_pair(row[f] + t, x0, x1);
+        acc[f] = fmaf(w0, x0, acc[f]);
       }
     }
 #pragma unroll
@@ -387,6 +440,8 @@ hipError_t launch_nyquist_batched(const BatchItemDev* d_items, int n_vec, int bl
       const __bf16* x = static_cast<const __bf16*>(xi);
       if (max_f_vec <= 1)
         hipLaunchKernelGGL((nyquist_batched_kernel<1, __bf16>), grid, blk, 0, s, d_items, n_vec, x);
+      else if (max_f_vec <= 2)
+        hipLaunchKernelGGL((nyquist_batched_kernel<2, __bf16>), grid, blk, 0, s, d_items, n_vec, x);
       else
         hipLaunchKernelGGL((nyquist_batched_kernel<kBatchVecMaxF, __bf16>), grid, blk, 0, s,
                            d_items, n_vec, x);
@@ -394,6 +449,9 @@ hipError_t launch_nyquist_batched(const BatchItemDev* d_items, int n_vec, int bl
       const _Float16* x = static_cast<const _Float16*>(xi);
       if (max_f_vec <= 1)
         hipLaunchKernelGGL((nyquist_batched_kernel<1, _Float16>), grid, blk, 0, s, d_items, n_vec,
+                           x);
+      else if (max_f_vec <= 2)
+        hipLaunchKernelGGL((nyquist_batched_kernel<2, _Float16>), grid, blk, 0, s, d_items, n_vec,
                            x);
       else
         hipLaunchKernelGGL((nyquist_batched_kernel<kBatchVecMaxF, _Float16>), grid, blk, 0, s,
