@@ -107,7 +107,6 @@ constexpr int kCRow = kCTile;  // LDS row length (elements, 128 bytes)
 constexpr int kCSteps = kCTile / 16;  // matrix-core steps per tile
 
 struct CachedArgs {
-  const double* unused;
   int64_t J;
   int F, S, Sw;
   int n_ct, n_fb;
@@ -284,7 +283,6 @@ hipError_t launch_nyquist_weights(const srp_geometry_s* g, int dtype, void* w, h
 hipError_t launch_nyquist_cached(const srp_geometry_s* g, const void* w, const void* xi, int F,
                                  int dtype, float* map, unsigned long long* keys, hipStream_t s) {
   CachedArgs a;
-  a.unused = nullptr;
   a.J = g->info.J;
   a.F = F;
   a.S = static_cast<int>(g->info.S);
