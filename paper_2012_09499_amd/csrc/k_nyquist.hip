@@ -73,23 +73,34 @@ __device__ __forceinline__ double pair_x(const NyqArgs& a, const PairDesc& pd, d
 }
 
 // Issues the asynchronous copy of one lag run of the samples into an LDS
-// tile [frame][lag] (row stride kStride): wave w copies rows w, w + 4, ...
-// below nrows = min(FB, F - f0), one lane per lag. Lanes past the run copy the
-// run's last element, so those slots hold finite values (they meet a zero
-// weight). Rows at or past F are not copied: each output frame depends only
-// on its own row, and outputs of such frames are discarded.
-__device__ __forceinline__ void stage_run(const NyqArgs& a, const LagRun& run, int off,
-                                          float* tile, int f0, int nrows, int wave, int lane) {
+// tile [frame][lag] (row stride kStride): wave w copies rows w, w + NW, ...,
+// one lane per lag, rows at or past F repeating the last frame (each output
+// frame depends only on its own row; outputs of frames past F are discarded).
+// Lanes at or past the run's end copy the column right after it. A run shorter
+// than kNyqRunMax ends at its pair window's end, and that column is the
+// layout's zero-filled gap (a window holds an odd number of lags, so at least
+// one gap column follows it); the only lag past a run that a step reads is
+// that one (an odd run's last step), so no weight needs a mask.
+template <int FB, int NW>
+__device__ __forceinline__ void stage_run(const NyqArgs& a, const RunRec& run, float* tile,
+                                          int f0, int nrows, int wave, int lane) {
   typedef __attribute__((address_space(3))) void* lds_ptr;
   if (run.len <= 0) return;
-  const int t = lane < run.len ? lane : run.len - 1;
-  const float* src = a.xi + (size_t)(f0 + wave) * a.S + off + run.t0 + t;
-  const size_t step = 4 * (size_t)a.S;
-  float* dst = tile + wave * kStride;
-  for (int f = wave; f < nrows; f += 4) {
-    __builtin_amdgcn_global_load_lds(src, (lds_ptr)dst, 4, 0, 0);
+  const int t = lane < run.len ? lane : run.len;
+  // row pointers advance by NW rows (scalar arithmetic); rows past the last
+  // frame are clamped to it. The empty asm keeps the compiler from hoisting
+  // the 32 clamped row addresses out of the run loop into spilled registers.
+  int nr = nrows, w = wave;
+  asm volatile("" : "+s"(nr), "+s"(w));
+  const float* src = a.xi + (size_t)(f0 + w) * a.S + run.off + run.t0;
+  const float* last = a.xi + (size_t)(f0 + nr - 1) * a.S + run.off + run.t0;
+  const size_t step = (size_t)NW * a.S;
+  float* dst = tile + w * kStride;
+#pragma unroll
+  for (int k = 0; k < FB / NW; ++k) {
+    const float* row = w + k * NW < nr ? src : last;
+    __builtin_amdgcn_global_load_lds(row + t, (lds_ptr)(dst + k * NW * kStride), 4, 0, 0);
     src += step;
-    dst += 4 * kStride;
   }
 }
 
@@ -104,42 +115,48 @@ struct LaneState {
   int cur_m, cur_p;
 };
 
+// x_p(i) of the lane's candidates for a new pair (float64), split into
+// rint(x), the float32 fraction and sin(pi xf) / pi.
+template <int CT>
+__device__ __forceinline__ void pair_setup(const NyqArgs& a, const RunRec& run,
+                                           LaneState<CT>& st) {
+  st.cur_p = run.p;
+  const double* pm = run.pm;
+  const double* pn = run.pn;
+  const bool new_m = run.m != st.cur_m;
+  st.cur_m = run.m;
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+    double x;
+    if (a.far_field) {
+      x = ((pm[0] - pn[0]) * st.qx[ct] + (pm[1] - pn[1]) * st.qy[ct] +
+           (pm[2] - pn[2]) * st.qz[ct]) * a.inv_cT;
+    } else {
+      if (new_m) st.rm[ct] = norm3(st.qx[ct] - pm[0], st.qy[ct] - pm[1], st.qz[ct] - pm[2]);
+      x = (st.rm[ct] - norm3(st.qx[ct] - pn[0], st.qy[ct] - pn[1], st.qz[ct] - pn[2])) *
+          a.inv_cT;
+    }
+    const double r = rint(x);
+    double f = x - r;
+    f = fabs(f) < 1e-30 ? 1e-30 : f;
+    st.xr[ct] = static_cast<int>(r);
+    st.xf[ct] = static_cast<float>(f);
+    st.sp[ct] = sinpi_over_pi(f);
+  }
+}
+
 // Contracts one staged lag run (tile = samples [frame][lag]) into acc.
 template <int CT, int FT>
-__device__ __forceinline__ void nyq_run(const NyqArgs& a, const double* __restrict__ mic,
-                                        const LagRun& run, const PairDesc& pd, LaneState<CT>& st,
+__device__ __forceinline__ void nyq_run(const NyqArgs& a, const RunRec& run, LaneState<CT>& st,
                                         const float* tile, int cl, int g,
                                         floatx16 (&acc)[CT][FT]) {
-  if (run.p != st.cur_p) {
-    st.cur_p = run.p;
-    const double* pm = mic + 3 * pd.m;
-    const double* pn = mic + 3 * pd.mp;
-    const bool new_m = pd.m != st.cur_m;
-    st.cur_m = pd.m;
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct) {
-      double x;
-      if (a.far_field) {
-        x = ((pm[0] - pn[0]) * st.qx[ct] + (pm[1] - pn[1]) * st.qy[ct] +
-             (pm[2] - pn[2]) * st.qz[ct]) * a.inv_cT;
-      } else {
-        if (new_m) st.rm[ct] = norm3(st.qx[ct] - pm[0], st.qy[ct] - pm[1], st.qz[ct] - pm[2]);
-        x = (st.rm[ct] - norm3(st.qx[ct] - pn[0], st.qy[ct] - pn[1], st.qz[ct] - pn[2])) *
-            a.inv_cT;
-      }
-      const double r = rint(x);
-      double f = x - r;
-      f = fabs(f) < 1e-30 ? 1e-30 : f;
-      st.xr[ct] = static_cast<int>(r);
-      st.xf[ct] = static_cast<float>(f);
-      st.sp[ct] = sinpi_over_pi(f);
-    }
-  }
+  if (run.len <= 0) return;
+  if (run.p != st.cur_p) pair_setup<CT>(a, run, st);
   // this lane's first lag in the run: n = -h + t0 + g
   float dnum[CT], qv[CT];
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) {
-    const int ia = st.xr[ct] + pd.h - run.t0 - g;
+    const int ia = st.xr[ct] + run.h - run.t0 - g;
     dnum[ct] = static_cast<float>(ia);
     qv[ct] = (ia & 1) ? -st.sp[ct] : st.sp[ct];
   }
@@ -153,11 +170,9 @@ __device__ __forceinline__ void nyq_run(const NyqArgs& a, const double* __restri
     const int sc = s < steps ? s : steps - 1;
 #pragma unroll
     for (int ft = 0; ft < FT; ++ft) av[ft] = arow[ft * 32 * kStride + 2 * sc];
-    const bool live = 2 * s + g < run.len;
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
-      const float wv = qv[ct] * __builtin_amdgcn_rcpf(dnum[ct] + st.xf[ct]);
-      w[ct] = live ? wv : 0.0f;
+      w[ct] = qv[ct] * __builtin_amdgcn_rcpf(dnum[ct] + st.xf[ct]);
       dnum[ct] -= 2.0f;
     }
   };
@@ -176,7 +191,7 @@ __device__ __forceinline__ void nyq_run(const NyqArgs& a, const double* __restri
     __builtin_amdgcn_sched_group_barrier(0x100, FT, 0);
 #pragma unroll
     for (int i = 1; i < CT * FT; ++i) {
-      __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, 1, 0);
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
     }
   };
@@ -197,13 +212,12 @@ __device__ __forceinline__ void nyq_run(const NyqArgs& a, const double* __restri
 // accumulator then holds one pair's contribution and is added into a second
 // float32 accumulator whenever the pair changes, so rounding grows with the
 // number of pairs and the steps per pair instead of with S.
-template <int CT, int FT, bool COMP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
-void nyquist_f32_kernel(NyqArgs a, const double* __restrict__ mic,
-                        const PairDesc* __restrict__ pairs, const LagRun* __restrict__ runs) {
+template <int CT, int FT, int NW, bool COMP>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void nyquist_f32_kernel(NyqArgs a, const RunRec* __restrict__ recs) {
   constexpr int FB = 32 * FT;
   constexpr int JW = 32 * CT;
-  constexpr int JB = 4 * JW;
+  constexpr int JB = NW * JW;
   // two staging tiles as distinct objects: the copy into one never aliases
   // the reads of the other, so reads wait only on their own tile's copy
   __shared__ float xs0[FB * kStride];
@@ -234,7 +248,7 @@ void nyquist_f32_kernel(NyqArgs a, const double* __restrict__ mic,
   }
   st.cur_m = -1;
   st.cur_p = -1;
-  for (int i = tid; i < FB; i += 256) kbest[i] = 0ull;
+  for (int i = tid; i < FB; i += 64 * NW) kbest[i] = 0ull;
 
   floatx16 acc[CT][FT];
   floatx16 hi[COMP ? CT : 1][COMP ? FT : 1];
@@ -265,37 +279,24 @@ void nyquist_f32_kernel(NyqArgs a, const double* __restrict__ mic,
     }
   };
 
-  {
-    const LagRun r0 = runs[0];
-    stage_run(a, r0, pairs[r0.p].off, xs0, f0, nrows, wave, lane);
-  }
+  stage_run<FB, NW>(a, recs[0], xs0, f0, nrows, wave, lane);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-
   for (int ri = 0; ri < a.n_runs; ri += 2) {
-    {  // even run: read xs0, copy the next run into xs1
-      const LagRun run = runs[ri];
-      const PairDesc pd = pairs[run.p];
-      const LagRun nx = runs[ri + 1];
-      const int nx_off = pairs[nx.p].off;
-      stage_run(a, nx, nx_off, xs1, f0, nrows, wave, lane);
-      fold(run.p);
-      nyq_run<CT, FT>(a, mic, run, pd, st, xs0, cl, g, acc);
-      __builtin_amdgcn_s_waitcnt(0);
-      __syncthreads();
-    }
-    {  // odd run: read xs1, copy the next run into xs0 (n_runs is even)
-      const LagRun run = runs[ri + 1];
-      const PairDesc pd = pairs[run.p];
-      if (ri + 2 < a.n_runs) {
-        const LagRun nx = runs[ri + 2];
-        stage_run(a, nx, pairs[nx.p].off, xs0, f0, nrows, wave, lane);
-      }
-      fold(run.p);
-      nyq_run<CT, FT>(a, mic, run, pd, st, xs1, cl, g, acc);
-      __builtin_amdgcn_s_waitcnt(0);
-      __syncthreads();
-    }
+    // even run: read xs0, copy the next run into xs1; odd run: read xs1,
+    // copy the next run into xs0 (the run count is even)
+    const RunRec r0 = recs[ri];
+    const RunRec r1 = recs[ri + 1];
+    stage_run<FB, NW>(a, r1, xs1, f0, nrows, wave, lane);
+    fold(r0.p);
+    nyq_run<CT, FT>(a, r0, st, xs0, cl, g, acc);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (ri + 2 < a.n_runs) stage_run<FB, NW>(a, recs[ri + 2], xs0, f0, nrows, wave, lane);
+    fold(r1.p);
+    nyq_run<CT, FT>(a, r1, st, xs1, cl, g, acc);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
   }
 
   if (COMP) {
@@ -331,7 +332,7 @@ void nyquist_f32_kernel(NyqArgs a, const double* __restrict__ mic,
   }
   if (a.keys) {
     __syncthreads();
-    for (int i = tid; i < FB; i += 256) {
+    for (int i = tid; i < FB; i += 64 * NW) {
       const unsigned long long k = kbest[i];
       if (k && f0 + i < a.F) atomicMax(a.keys + 2 * (size_t)(f0 + i), k);
     }
@@ -404,27 +405,7 @@ __device__ __forceinline__ void nyq_run_mx(const NyqArgs& a, const RunRec& run,
   typedef typename MxVec<T>::type vec8;
   if (run.len <= 0) return;
   const RunRec& pd = run;
-  if (run.p != st.cur_p) {
-    st.cur_p = run.p;
-    const double* pm = run.pm;
-    const double* pn = run.pn;
-    const bool new_m = pd.m != st.cur_m;
-    st.cur_m = pd.m;
-    double x;
-    if (a.far_field) {
-      x = ((pm[0] - pn[0]) * st.qx[0] + (pm[1] - pn[1]) * st.qy[0] +
-           (pm[2] - pn[2]) * st.qz[0]) * a.inv_cT;
-    } else {
-      if (new_m) st.rm[0] = norm3(st.qx[0] - pm[0], st.qy[0] - pm[1], st.qz[0] - pm[2]);
-      x = (st.rm[0] - norm3(st.qx[0] - pn[0], st.qy[0] - pn[1], st.qz[0] - pn[2])) * a.inv_cT;
-    }
-    const double r = rint(x);
-    double f = x - r;
-    f = fabs(f) < 1e-30 ? 1e-30 : f;
-    st.xr[0] = static_cast<int>(r);
-    st.xf[0] = static_cast<float>(f);
-    st.sp[0] = sinpi_over_pi(f);
-  }
+  if (run.p != st.cur_p) pair_setup<1>(a, run, st);
   // lane's first lag of step 0: n = -h + t0 + 8g;  d_j = (ia - 16 s - j) + xf,
   // the integer part formed exactly first so that the only rounding is the
   // final addition of xf (d_j is then never 0, since xf != 0)
@@ -697,18 +678,18 @@ hipError_t launch_nyquist(const srp_geometry_s* g, const void* xi, int F, int dt
     int64_t samples = 0;
     for (const PairDesc& pd : g->pairs) samples += 2 * pd.h + 1;
     if (samples <= kNyqPlainSumMax)
-      launch_frame_blocks<4>(F, a, [&](auto ft, const NyqArgs& b, int fblocks) {
-        constexpr int CT = 2, JB = 4 * 32 * CT;
+      launch_frame_blocks<8>(F, a, [&](auto ft, const NyqArgs& b, int fblocks) {
+        constexpr int CT = 1, NW = 8, JB = NW * 32 * CT;
         const dim3 grid(static_cast<unsigned>((b.J + JB - 1) / JB), fblocks);
-        hipLaunchKernelGGL((nyquist_f32_kernel<CT, decltype(ft)::value, false>), grid, dim3(256),
-                           0, s, b, b.mic, b.pairs, b.runs);
+        hipLaunchKernelGGL((nyquist_f32_kernel<CT, decltype(ft)::value, NW, false>), grid,
+                           dim3(64 * NW), 0, s, b, g->d_nyq_recs);
       });
     else
       launch_frame_blocks<4>(F, a, [&](auto ft, const NyqArgs& b, int fblocks) {
-        constexpr int CT = 1, JB = 4 * 32 * CT;
+        constexpr int CT = 1, NW = 4, JB = NW * 32 * CT;
         const dim3 grid(static_cast<unsigned>((b.J + JB - 1) / JB), fblocks);
-        hipLaunchKernelGGL((nyquist_f32_kernel<CT, decltype(ft)::value, true>), grid, dim3(256),
-                           0, s, b, b.mic, b.pairs, b.runs);
+        hipLaunchKernelGGL((nyquist_f32_kernel<CT, decltype(ft)::value, NW, true>), grid,
+                           dim3(64 * NW), 0, s, b, g->d_nyq_recs);
       });
     return hipGetLastError();
   }

@@ -211,8 +211,16 @@ srp_status srp_geometry(const double* mic_xyz, int32_t M, const double* cand_xyz
     const int W = 2 * g->pairs[p].h + 1;
     for (int t0 = 0; t0 < W; t0 += kGccLagTile)
       g->gcc_tiles.push_back(LagRun{p, t0, W - t0 < kGccLagTile ? W - t0 : kGccLagTile, 0});
-    for (int t0 = 0; t0 < W; t0 += kNyqRunMax)
-      g->nyq_runs.push_back(LagRun{p, t0, W - t0 < kNyqRunMax ? W - t0 : kNyqRunMax, 0});
+    // a window longer than one run is split into runs of about equal length
+    // (all but the last a multiple of kSampleAlign lags, so every run starts
+    // on an aligned column), not into full runs and a short remainder: each
+    // run costs a fixed copy and synchronisation, which a short run does not
+    // cover with work
+    const int nr = (W + kNyqRunMax - 1) / kNyqRunMax;
+    const int per = (W + nr - 1) / nr;
+    const int run_len = (per + kSampleAlign - 1) / kSampleAlign * kSampleAlign;
+    for (int t0 = 0; t0 < W; t0 += run_len)
+      g->nyq_runs.push_back(LagRun{p, t0, W - t0 < run_len ? W - t0 : run_len, 0});
   }
   // the FP32 interpolation kernel consumes runs two at a time: pad with an
   // empty run of the last pair (no lags, no copy, no pair change)
