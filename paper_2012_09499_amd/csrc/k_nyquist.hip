@@ -72,35 +72,88 @@ __device__ __forceinline__ double pair_x(const NyqArgs& a, const PairDesc& pd, d
   return (sqrt(ax * ax + ay * ay + az * az) - sqrt(bx * bx + by * by + bz * bz)) * a.inv_cT;
 }
 
-// Issues the asynchronous copy of one lag run of the samples into an LDS
-// tile [frame][lag] (row stride kStride): wave w copies rows w, w + NW, ...,
-// one lane per lag, rows at or past F repeating the last frame (each output
-// frame depends only on its own row; outputs of frames past F are discarded).
-// Lanes at or past the run's end copy the column right after it. A run shorter
-// than kNyqRunMax ends at its pair window's end, and that column is the
-// layout's zero-filled gap (a window holds an odd number of lags, so at least
-// one gap column follows it); the only lag past a run that a step reads is
-// that one (an odd run's last step), so no weight needs a mask.
+// FP32 staging tile: frame tiles of 32 rows [frame][64 lags], 256 bytes per
+// row, the tiles kBlk32 floats apart (16 bytes of padding between tiles, so
+// the compiler never merges a step's reads of different tiles into one
+// instruction, which would hide from it which buffer they read). Within a row,
+// 16-byte chunk c (lags 4c .. 4c+3) is stored at chunk c ^ (R & 15): a step's
+// read has each wave half read the same lags from 32 rows, and the swizzle
+// puts 16 consecutive rows on 16 different bank groups.
+constexpr int kRow32 = kNyqRunMax;   // floats per LDS row
+constexpr int kBlk32 = 32 * kRow32 + 4;  // floats per 32-row frame tile
+
+// Per-lane constants of the FP32 staging copies. One copy instruction moves
+// 4 rows (64 lanes x 16 bytes, landing in lane order): lane i fills chunk
+// i & 15 of row 4G + (i >> 4) of row group G. Wave w copies the groups
+// G = w, w + NW, ...; with NW a multiple of 4, G & 3 = w & 3, so the logical
+// chunk a lane loads is the same for all its groups and runs.
+struct Stage32 {
+  int jr;         // row of the lane within a group
+  int lchunk;     // logical chunk this lane loads
+  unsigned roff;  // jr rows, in bytes
+};
+
+template <int NW>
+__device__ __forceinline__ Stage32 stage32_init(const NyqArgs& a, int wave, int lane) {
+  static_assert(NW % 4 == 0, "row groups of a wave must share their swizzle");
+  Stage32 sg;
+  sg.jr = lane >> 4;
+  sg.lchunk = (lane & 15) ^ (4 * (wave & 3) + sg.jr);
+  sg.roff = static_cast<unsigned>(sg.jr) * 4u * static_cast<unsigned>(a.S);
+  return sg;
+}
+
+// Issues the asynchronous copy of one lag run of the samples into a staging
+// tile. The steps read lags 0 .. 2 ceil(len / 2) - 1 of the run, all in chunks
+// 0 .. (len - 1) / 4; chunks past those repeat the last one (they are never
+// read). A run of odd length ends at its pair window's end (runs before the
+// last one of a window are multiples of 8 long), and its lag len, which the
+// last step reads, is then the layout's zero-filled gap after the window (a
+// window holds an odd number of lags and starts at a multiple of 8), so no
+// weight needs a mask.
 template <int FB, int NW>
-__device__ __forceinline__ void stage_run(const NyqArgs& a, const RunRec& run, float* tile,
-                                          int f0, int nrows, int wave, int lane) {
+__device__ __forceinline__ void stage_run(const NyqArgs& a, const RunRec& run, const Stage32& sg,
+                                          float* tile, int f0, int nrows, int wave) {
   typedef __attribute__((address_space(3))) void* lds_ptr;
+  constexpr int kGroups = FB / (4 * NW);  // row groups per wave
   if (run.len <= 0) return;
-  const int t = lane < run.len ? lane : run.len;
-  // row pointers advance by NW rows (scalar arithmetic); rows past the last
-  // frame are clamped to it. The empty asm keeps the compiler from hoisting
-  // the 32 clamped row addresses out of the run loop into spilled registers.
+  const int lc = (run.len - 1) >> 2;  // last chunk the steps read
+  const unsigned cb = 16u * static_cast<unsigned>(sg.lchunk < lc ? sg.lchunk : lc);
+  // group base rows advance by 4 NW rows (scalar arithmetic). The empty asm
+  // keeps the compiler from hoisting the per-group addresses out of the run
+  // loop into spilled registers.
   int nr = nrows, w = wave;
   asm volatile("" : "+s"(nr), "+s"(w));
-  const float* src = a.xi + (size_t)(f0 + w) * a.S + run.off + run.t0;
-  const float* last = a.xi + (size_t)(f0 + nr - 1) * a.S + run.off + run.t0;
-  const size_t step = (size_t)NW * a.S;
-  float* dst = tile + w * kStride;
+  const float* col = a.xi + run.off + run.t0;
+  const char* base = reinterpret_cast<const char*>(col + (size_t)(f0 + 4 * w) * a.S);
+  const size_t gstep = (size_t)4 * NW * a.S * sizeof(float);
+  if (nr == FB) {
+    const unsigned vo = sg.roff + cb;  // per-lane 32-bit offset from a scalar base
 #pragma unroll
-  for (int k = 0; k < FB / NW; ++k) {
-    const float* row = w + k * NW < nr ? src : last;
-    __builtin_amdgcn_global_load_lds(row + t, (lds_ptr)(dst + k * NW * kStride), 4, 0, 0);
-    src += step;
+    for (int k = 0; k < kGroups; ++k) {
+      const int G = w + k * NW;
+      float* dst = tile + (G >> 3) * kBlk32 + 4 * (G & 7) * kRow32;
+      __builtin_amdgcn_global_load_lds(reinterpret_cast<const float*>(base + vo), (lds_ptr)dst,
+                                       16, 0, 0);
+      base += gstep;
+    }
+  } else {
+    // the block's last frames: rows at or past F repeat the last frame (their
+    // outputs are discarded); a group that starts past it is based at the
+    // last frame, so offsets from a group's base row are never negative
+    const char* lastrow = reinterpret_cast<const char*>(col + (size_t)(f0 + nr - 1) * a.S);
+#pragma unroll
+    for (int k = 0; k < kGroups; ++k) {
+      const int G = w + k * NW;
+      const int g0 = 4 * G;
+      const int gb = g0 < nr ? g0 : nr - 1;
+      const int r = g0 + sg.jr < nr ? g0 + sg.jr : nr - 1;
+      const unsigned vo = static_cast<unsigned>(r - gb) * 4u * static_cast<unsigned>(a.S) + cb;
+      float* dst = tile + (G >> 3) * kBlk32 + 4 * (G & 7) * kRow32;
+      __builtin_amdgcn_global_load_lds(reinterpret_cast<const float*>((g0 < nr ? base : lastrow) + vo),
+                                       (lds_ptr)dst, 16, 0, 0);
+      base += gstep;
+    }
   }
 }
 
@@ -160,16 +213,22 @@ __device__ __forceinline__ void nyq_run(const NyqArgs& a, const RunRec& run, Lan
     dnum[ct] = static_cast<float>(ia);
     qv[ct] = (ia & 1) ? -st.sp[ct] : st.sp[ct];
   }
-  const float* arow = tile + cl * kStride + g;
+  // lag t = 2 s + g of row R: chunk (s >> 1) ^ (R & 15), element 2 (s & 1) + g;
+  // R & 15 = cl & 15 in every frame tile
+  const float* arow = tile + cl * kRow32 + g;
+  const int swz4 = (cl & 15) << 2;  // the row's chunk swizzle, in floats
   const int steps = (run.len + 1) >> 1;
   // software pipeline, two steps per iteration with ping-pong operand sets:
   // the LDS samples and weights of the next step are fetched and formed while
-  // the matrix cores work on the current one
+  // the matrix cores work on the current one. Steps 2k and 2k + 1 read the
+  // same chunk (elements 0 + g and 2 + g); a read past the run (the pipeline's
+  // look-ahead after its last step) stays inside the row and is never used.
   float av0[FT], av1[FT], w0[CT], w1[CT];
-  auto fetch = [&](int s, float (&av)[FT], float (&w)[CT]) {
-    const int sc = s < steps ? s : steps - 1;
+  auto load = [&](const float* src, float (&av)[FT]) {
 #pragma unroll
-    for (int ft = 0; ft < FT; ++ft) av[ft] = arow[ft * 32 * kStride + 2 * sc];
+    for (int ft = 0; ft < FT; ++ft) av[ft] = src[ft * kBlk32];
+  };
+  auto weights = [&](float (&w)[CT]) {
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
       w[ct] = qv[ct] * __builtin_amdgcn_rcpf(dnum[ct] + st.xf[ct]);
@@ -185,9 +244,11 @@ __device__ __forceinline__ void nyq_run(const NyqArgs& a, const RunRec& run, Lan
   };
   auto order = [&]() {
     // issue order: one matrix-core instruction (its operands were read a
-    // half-iteration earlier), then the next step's LDS reads, then the other
-    // matrix-core instructions with the weight arithmetic slotted between them
+    // half-iteration earlier), the read address, the next step's LDS reads,
+    // then the other matrix-core instructions with the weight arithmetic
+    // slotted between them
     __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
     __builtin_amdgcn_sched_group_barrier(0x100, FT, 0);
 #pragma unroll
     for (int i = 1; i < CT * FT; ++i) {
@@ -195,13 +256,18 @@ __device__ __forceinline__ void nyq_run(const NyqArgs& a, const RunRec& run, Lan
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
     }
   };
-  fetch(0, av0, w0);
+  const float* src = arow + swz4;  // chunk 0
+  load(src, av0);
+  weights(w0);
   int s = 0;
   for (; s + 1 < steps; s += 2) {
-    fetch(s + 1, av1, w1);
+    load(src + 2, av1);
+    weights(w1);
     contract(av0, w0);
     order();
-    fetch(s + 2, av0, w0);
+    src = arow + (((((s + 2) >> 1) & 15) << 2) ^ swz4);
+    load(src, av0);
+    weights(w0);
     contract(av1, w1);
     order();
   }
@@ -220,8 +286,8 @@ void nyquist_f32_kernel(NyqArgs a, const RunRec* __restrict__ recs) {
   constexpr int JB = NW * JW;
   // two staging tiles as distinct objects: the copy into one never aliases
   // the reads of the other, so reads wait only on their own tile's copy
-  __shared__ float xs0[FB * kStride];
-  __shared__ float xs1[FB * kStride];
+  __shared__ __attribute__((aligned(16))) float xs0[FT * kBlk32];
+  __shared__ __attribute__((aligned(16))) float xs1[FT * kBlk32];
   __shared__ unsigned long long kbest[FB];
 
   const int tid = threadIdx.x;
@@ -279,7 +345,8 @@ void nyquist_f32_kernel(NyqArgs a, const RunRec* __restrict__ recs) {
     }
   };
 
-  stage_run<FB, NW>(a, recs[0], xs0, f0, nrows, wave, lane);
+  const Stage32 sg = stage32_init<NW>(a, wave, lane);
+  stage_run<FB, NW>(a, recs[0], sg, xs0, f0, nrows, wave);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   for (int ri = 0; ri < a.n_runs; ri += 2) {
@@ -287,12 +354,12 @@ void nyquist_f32_kernel(NyqArgs a, const RunRec* __restrict__ recs) {
     // copy the next run into xs0 (the run count is even)
     const RunRec r0 = recs[ri];
     const RunRec r1 = recs[ri + 1];
-    stage_run<FB, NW>(a, r1, xs1, f0, nrows, wave, lane);
+    stage_run<FB, NW>(a, r1, sg, xs1, f0, nrows, wave);
     fold(r0.p);
     nyq_run<CT, FT>(a, r0, st, xs0, cl, g, acc);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (ri + 2 < a.n_runs) stage_run<FB, NW>(a, recs[ri + 2], xs0, f0, nrows, wave, lane);
+    if (ri + 2 < a.n_runs) stage_run<FB, NW>(a, recs[ri + 2], sg, xs0, f0, nrows, wave);
     fold(r1.p);
     nyq_run<CT, FT>(a, r1, st, xs1, cl, g, acc);
     __builtin_amdgcn_s_waitcnt(0);
