@@ -166,6 +166,9 @@ struct LaneState {
   float xf[CT];                   // x - rint(x)
   float sp[CT];                   // sin(pi xf) / pi
   int cur_m, cur_p;
+  // the prepared run: sinc denominator of the lane's next lag (integer part),
+  // sign-carrying numerator, and the first step's weight
+  float dnum[CT], qv[CT], w0[CT];
 };
 
 // x_p(i) of the lane's candidates for a new pair (float64), split into
@@ -198,20 +201,37 @@ __device__ __forceinline__ void pair_setup(const NyqArgs& a, const RunRec& run,
   }
 }
 
-// Contracts one staged lag run (tile = samples [frame][lag]) into acc.
-template <int CT, int FT>
-__device__ __forceinline__ void nyq_run(const NyqArgs& a, const RunRec& run, LaneState<CT>& st,
-                                        const float* tile, int cl, int g,
-                                        floatx16 (&acc)[CT][FT]) {
+// Everything of a run that does not need its staged samples: the pair's
+// TDOA split (when the pair changes) and the first step's weights. Called
+// before the barrier that publishes the run's samples, so this latency
+// overlaps the previous run's last matrix-core instructions.
+template <int CT>
+__device__ __forceinline__ void nyq_prepare(const NyqArgs& a, const RunRec& run,
+                                            LaneState<CT>& st, int g) {
   if (run.len <= 0) return;
   if (run.p != st.cur_p) pair_setup<CT>(a, run, st);
   // this lane's first lag in the run: n = -h + t0 + g
-  float dnum[CT], qv[CT];
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) {
     const int ia = st.xr[ct] + run.h - run.t0 - g;
-    dnum[ct] = static_cast<float>(ia);
-    qv[ct] = (ia & 1) ? -st.sp[ct] : st.sp[ct];
+    st.dnum[ct] = static_cast<float>(ia);
+    st.qv[ct] = (ia & 1) ? -st.sp[ct] : st.sp[ct];
+    st.w0[ct] = st.qv[ct] * __builtin_amdgcn_rcpf(st.dnum[ct] + st.xf[ct]);
+    st.dnum[ct] -= 2.0f;
+  }
+}
+
+// Contracts one staged lag run (tile = samples [frame][lag]) into acc; the
+// run was prepared by nyq_prepare.
+template <int CT, int FT>
+__device__ __forceinline__ void nyq_run(const RunRec& run, LaneState<CT>& st, const float* tile,
+                                        int cl, int g, floatx16 (&acc)[CT][FT]) {
+  if (run.len <= 0) return;
+  float dnum[CT], qv[CT];
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+    dnum[ct] = st.dnum[ct];
+    qv[ct] = st.qv[ct];
   }
   // lag t = 2 s + g of row R: chunk (s >> 1) ^ (R & 15), element 2 (s & 1) + g;
   // R & 15 = cl & 15 in every frame tile
@@ -258,7 +278,8 @@ __device__ __forceinline__ void nyq_run(const NyqArgs& a, const RunRec& run, Lan
   };
   const float* src = arow + swz4;  // chunk 0
   load(src, av0);
-  weights(w0);
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) w0[ct] = st.w0[ct];
   int s = 0;
   for (; s + 1 < steps; s += 2) {
     load(src + 2, av1);
@@ -332,8 +353,9 @@ void nyquist_f32_kernel(NyqArgs a, const RunRec* __restrict__ recs) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) hi[ct][ft][r] = 0.0f;
   }
+  int acc_p = -1;  // the pair whose terms acc holds (two-level sums)
   auto fold = [&](int p) {
-    if (COMP && p != st.cur_p && st.cur_p >= 0) {
+    if (COMP && p != acc_p && acc_p >= 0) {
 #pragma unroll
       for (int ct = 0; ct < (COMP ? CT : 1); ++ct)
 #pragma unroll
@@ -343,25 +365,32 @@ void nyquist_f32_kernel(NyqArgs a, const RunRec* __restrict__ recs) {
           for (int r = 0; r < 16; ++r) acc[ct][ft][r] = 0.0f;
         }
     }
+    acc_p = p;
   };
 
   const Stage32 sg = stage32_init<NW>(a, wave, lane);
   stage_run<FB, NW>(a, recs[0], sg, xs0, f0, nrows, wave);
+  nyq_prepare<CT>(a, recs[0], st, g);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   for (int ri = 0; ri < a.n_runs; ri += 2) {
     // even run: read xs0, copy the next run into xs1; odd run: read xs1,
-    // copy the next run into xs0 (the run count is even)
+    // copy the next run into xs0 (the run count is even). Each run is
+    // prepared before the barrier ahead of it.
     const RunRec r0 = recs[ri];
     const RunRec r1 = recs[ri + 1];
     stage_run<FB, NW>(a, r1, sg, xs1, f0, nrows, wave);
     fold(r0.p);
-    nyq_run<CT, FT>(a, r0, st, xs0, cl, g, acc);
+    nyq_run<CT, FT>(r0, st, xs0, cl, g, acc);
+    nyq_prepare<CT>(a, r1, st, g);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (ri + 2 < a.n_runs) stage_run<FB, NW>(a, recs[ri + 2], sg, xs0, f0, nrows, wave);
+    const bool more = ri + 2 < a.n_runs;
+    const RunRec r2 = recs[more ? ri + 2 : ri];
+    if (more) stage_run<FB, NW>(a, r2, sg, xs0, f0, nrows, wave);
     fold(r1.p);
-    nyq_run<CT, FT>(a, r1, st, xs1, cl, g, acc);
+    nyq_run<CT, FT>(r1, st, xs1, cl, g, acc);
+    if (more) nyq_prepare<CT>(a, r2, st, g);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
   }
