@@ -509,7 +509,8 @@ __device__ __forceinline__ void nyq_run_mx(const NyqArgs& a, const RunRec& run,
   const float qs = (ia & 1) ? -st.sp[0] : st.sp[0];
   const float xf = st.xf[0];
   const int steps = (run.len + 15) >> 4;
-  const int rowsw = (cl >> 1) & 7;
+  // chunk 2 s + g of row cl sits at (2 s + g) ^ rowsw = 2 s ^ gsw (2 s is even)
+  const int gsw = g ^ ((cl >> 1) & 7);
   const T* trow = tile + cl * kRowH;
   // software pipeline with ping-pong operand sets: the LDS samples and the
   // weights of the next step are fetched and formed while the matrix cores
@@ -517,10 +518,10 @@ __device__ __forceinline__ void nyq_run_mx(const NyqArgs& a, const RunRec& run,
   // never contracted)
   auto fetch = [&](int s, vec8 (&av)[FT], vec8& wv) {
     const int sc = s < steps ? s : steps - 1;
-    const int pc = (2 * sc + g) ^ rowsw;
+    const T* src = trow + 8 * ((2 * sc) ^ gsw);
 #pragma unroll
     for (int ft = 0; ft < FT; ++ft)
-      av[ft] = *reinterpret_cast<const vec8*>(trow + ft * 32 * kRowH + 8 * pc);
+      av[ft] = *reinterpret_cast<const vec8*>(src + ft * 32 * kRowH);
     const float base = static_cast<float>(ia - 16 * s);
     float w[8];
 #pragma unroll
@@ -539,9 +540,11 @@ __device__ __forceinline__ void nyq_run_mx(const NyqArgs& a, const RunRec& run,
     for (int ft = 0; ft < FT; ++ft) acc[ft] = MxVec<T>::mfma(av[ft], wv, acc[ft]);
   };
   auto order = [&]() {
-    // issue order: one matrix-core instruction, the next step's LDS reads,
-    // then the weight arithmetic slotted between the remaining instructions
+    // issue order: one matrix-core instruction, the read address, the next
+    // step's LDS reads, then the weight arithmetic slotted between the
+    // remaining instructions
     __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
     __builtin_amdgcn_sched_group_barrier(0x100, FT, 0);
 #pragma unroll
     for (int i = 1; i < FT; ++i) {
