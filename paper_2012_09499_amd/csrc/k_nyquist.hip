@@ -116,6 +116,7 @@ __device__ __forceinline__ void stage_run(const NyqArgs& a, const RunRec& run, c
                                           float* tile, int f0, int nrows, int wave) {
   typedef __attribute__((address_space(3))) void* lds_ptr;
   constexpr int kGroups = FB / (4 * NW);  // row groups per wave
+  static_assert(FB % (4 * NW) == 0, "every wave copies the same number of row groups");
   if (run.len <= 0) return;
   const int lc = (run.len - 1) >> 2;  // last chunk the steps read
   const unsigned cb = 16u * static_cast<unsigned>(sg.lchunk < lc ? sg.lchunk : lc);
@@ -470,27 +471,44 @@ template <> struct MxVec<_Float16> {
 constexpr int kRowH = kNyqRunMax;  // elements per LDS row (64 lags, 128 bytes)
 
 // Copies one lag run into the swizzled tile [FB][64]: each instruction moves
-// 8 rows (64 lanes x 16 bytes); wave w handles rows 8w, 8w + 32, ...
+// 8 rows (64 lanes x 16 bytes); wave w handles the row groups 8w, 8w + 8 NW,
+// ... Straight-line code: rows at or past F repeat the last frame (their
+// outputs are discarded), and chunks past the run are copied from a zeroed
+// buffer, so lags past the run need no weight mask (a run's last chunk ends at
+// a window end, whose padding is zero). With NW even, a lane's logical chunk
+// c = cp ^ ((row >> 1) & 7) is the same in all of its wave's row groups.
 template <typename T, int FB, int NW>
 __device__ __forceinline__ void stage_run_mx(const T* __restrict__ xi, const float* zero, int S,
                                              int F, int f0, int nrows, const RunRec& run,
                                              T* tile, int wave, int lane) {
   typedef __attribute__((address_space(3))) void* lds_ptr;
-  const int off = run.off;
+  static_assert(NW % 2 == 0, "row groups of a wave must share their swizzle");
+  // row groups per wave; when FB is not a multiple of 8 NW rows (a tail block
+  // of an odd number of 32-frame tiles) the last round of groups is partial
+  constexpr int kGroups = (FB + 8 * NW - 1) / (8 * NW);
   if (run.len <= 0) return;
   const int nch = (run.len + 7) >> 3;            // 16-byte chunks holding the run
   const int rsub = lane >> 3;                    // row within the 8-row group
   const int cp = lane & 7;                       // physical chunk in LDS
-  for (int rb = 8 * wave; rb < nrows; rb += 8 * NW) {
+  // the empty asm keeps the compiler from hoisting per-group values out of
+  // the run loop into spilled registers
+  int nr = nrows, w = wave;
+  asm volatile("" : "+s"(nr), "+s"(w));
+  const int c = cp ^ ((((8 * w) >> 1) + (rsub >> 1)) & 7);  // logical chunk stored at cp
+  // branch-free choice between the sample chunk and the zero buffer: a lane
+  // past the run adds nothing to the zero buffer's address
+  const uint64_t za = reinterpret_cast<uint64_t>(zero);
+  const uint64_t keep = c < nch ? ~0ull : 0ull;
+  const uint64_t col = reinterpret_cast<uint64_t>(xi + run.off + run.t0 + 8 * c) - za;
+#pragma unroll
+  for (int k = 0; k < kGroups; ++k) {
+    const int rb = 8 * (w + k * NW);
+    if (FB % (8 * NW) != 0 && rb >= FB) break;  // (uniform) the tile has no such group
     const int row = rb + rsub;
-    const int c = cp ^ ((row >> 1) & 7);         // logical chunk stored at cp
-    const int rr = row < nrows ? row : nrows - 1;
-    // chunks past the run hold zeros, so lags past the run need no weight mask
-    // (a run's last chunk ends at a window end, whose padding is zero)
-    const void* src = c < nch
-        ? static_cast<const void*>(xi + (size_t)(f0 + rr) * S + off + run.t0 + 8 * c)
-        : static_cast<const void*>(zero);
-    __builtin_amdgcn_global_load_lds(src, (lds_ptr)(tile + rb * kRowH), 16, 0, 0);
+    const int rr = row < nr ? row : nr - 1;
+    const uint64_t d = col + (uint64_t)(f0 + rr) * (uint64_t)S * sizeof(T);
+    __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(za + (d & keep)),
+                                     (lds_ptr)(tile + rb * kRowH), 16, 0, 0);
   }
 }
 
