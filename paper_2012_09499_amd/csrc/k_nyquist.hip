@@ -111,13 +111,19 @@ __device__ __forceinline__ Stage32 stage32_init(const NyqArgs& a, int wave, int 
 // last step reads, is then the layout's zero-filled gap after the window (a
 // window holds an odd number of lags and starts at a multiple of 8), so no
 // weight needs a mask.
-template <int FB, int NW>
+//
+// Only the first 4 waves copy (one per SIMD, waves w and w + 4 sharing SIMD
+// w): right after a barrier, each SIMD then has one wave issuing its copies
+// and one issuing matrix-core instructions, instead of both stalled on a
+// burst of copies.
+template <int FB, int NW0>
 __device__ __forceinline__ void stage_run(const NyqArgs& a, const RunRec& run, const Stage32& sg,
                                           float* tile, int f0, int nrows, int wave) {
   typedef __attribute__((address_space(3))) void* lds_ptr;
-  constexpr int kGroups = FB / (4 * NW);  // row groups per wave
-  static_assert(FB % (4 * NW) == 0, "every wave copies the same number of row groups");
-  if (run.len <= 0) return;
+  constexpr int NW = 4;                   // copying waves
+  constexpr int kGroups = FB / (4 * NW);  // row groups per copying wave
+  static_assert(FB % (4 * NW) == 0, "every copying wave copies the same number of row groups");
+  if (run.len <= 0 || wave >= NW) return;
   const int lc = (run.len - 1) >> 2;  // last chunk the steps read
   const unsigned cb = 16u * static_cast<unsigned>(sg.lchunk < lc ? sg.lchunk : lc);
   // group base rows advance by 4 NW rows (scalar arithmetic). The empty asm
@@ -471,22 +477,24 @@ template <> struct MxVec<_Float16> {
 constexpr int kRowH = kNyqRunMax;  // elements per LDS row (64 lags, 128 bytes)
 
 // Copies one lag run into the swizzled tile [FB][64]: each instruction moves
-// 8 rows (64 lanes x 16 bytes); wave w handles the row groups 8w, 8w + 8 NW,
-// ... Straight-line code: rows at or past F repeat the last frame (their
-// outputs are discarded), and chunks past the run are copied from a zeroed
-// buffer, so lags past the run need no weight mask (a run's last chunk ends at
-// a window end, whose padding is zero). With NW even, a lane's logical chunk
+// 8 rows (64 lanes x 16 bytes). Only the first NW = 4 waves copy (one per
+// SIMD; see stage_run); wave w handles the row groups 8w, 8w + 8 NW, ...
+// Straight-line code: rows at or past F repeat the last frame (their outputs
+// are discarded), and chunks past the run are copied from a zeroed buffer, so
+// lags past the run need no weight mask (a run's last chunk ends at a window
+// end, whose padding is zero). With NW even, a lane's logical chunk
 // c = cp ^ ((row >> 1) & 7) is the same in all of its wave's row groups.
-template <typename T, int FB, int NW>
+template <typename T, int FB, int NW0>
 __device__ __forceinline__ void stage_run_mx(const T* __restrict__ xi, const float* zero, int S,
                                              int F, int f0, int nrows, const RunRec& run,
                                              T* tile, int wave, int lane) {
   typedef __attribute__((address_space(3))) void* lds_ptr;
+  constexpr int NW = 4;  // copying waves
   static_assert(NW % 2 == 0, "row groups of a wave must share their swizzle");
   // row groups per wave; when FB is not a multiple of 8 NW rows (a tail block
   // of an odd number of 32-frame tiles) the last round of groups is partial
   constexpr int kGroups = (FB + 8 * NW - 1) / (8 * NW);
-  if (run.len <= 0) return;
+  if (run.len <= 0 || wave >= NW) return;
   const int nch = (run.len + 7) >> 3;            // 16-byte chunks holding the run
   const int rsub = lane >> 3;                    // row within the 8-row group
   const int cp = lane & 7;                       // physical chunk in LDS
