@@ -16,7 +16,9 @@ candidate grids) arrive as requests. The server
   in that type, float32 accumulation), chosen per server;
 * keeps two batch slots on two HIP streams, so a batch is assembled and its
   spectra run while the previous batch's maps are still on the GPU; requests
-  that arrive meanwhile join the next batch (continuous batching);
+  that arrive meanwhile join the next batch (continuous batching); the slots'
+  device and pinned host buffers are grown once after admissions to hold the
+  largest batch, so no batch allocates memory while requests wait;
 * validates each request (known, admitted array; frame shape; finite values)
   and fails that request alone on error; a failed batch launch fails only the
   requests of that batch;
@@ -124,6 +126,7 @@ class SrpServer:
         self.batches = 0
         self.batch_frames: List[int] = []
         self._seq = 0
+        self._reserved = True  # slot buffers cover max_f frames of every admitted array
 
     # ------------------------------------------------------------ admission
     def open_array(self, array_id, mic_xyz, candidates, *, fs, L, c=343.0, n_aux=2,
@@ -152,6 +155,7 @@ class SrpServer:
         a.need = need
         self.arrays[array_id] = a
         self.used += need
+        self._reserved = False
 
     def close_array(self, array_id):
         a = self.arrays.pop(array_id, None)
@@ -201,6 +205,8 @@ class SrpServer:
 
         Returns the number of requests completed by this call.
         """
+        if not self._reserved:
+            self._reserve()
         done = self._poll()
         if any(a.pending for a in self.arrays.values()):
             for slot in self.slots:
@@ -231,6 +237,34 @@ class SrpServer:
                         n += 1
                 slot.event, slot.requests = None, []
         return n
+
+    def _reserve(self):
+        """Grows every slot's buffers to hold max_f frames of every admitted array
+        (the share footprint() budgets), so that no batch allocates device or
+        pinned host memory while requests wait (an allocation can stall the
+        device for milliseconds)."""
+        import torch
+        fr = ws = psi = xi = pk = 0
+        for a in self.arrays.values():
+            F = self.max_f
+            fr += F * a.M * a.L
+            ws += (F * a.M * a.K * 8 + 255) // 256 * 256
+            psi += F * a.P * a.K
+            xi += F * a.S
+            pk += F
+        for slot in self.slots:
+            slot.host(fr)
+            slot.buf("frames", fr, torch.float32)
+            slot.buf("ws", ws, torch.uint8)
+            slot.buf("psi", psi, torch.complex64)
+            slot.buf("xi", xi, self.sample_dtype)
+            slot.buf("peaks", 2 * pk, torch.int64)
+            slot.buf("items", S.batched_workspace_bytes(len(self.arrays)), torch.uint8)
+            if slot.cap.get("peaks_host", 0) < 2 * pk:
+                slot.bufs["peaks_host"] = torch.empty(max(2 * pk, 256), dtype=torch.int64,
+                                                      pin_memory=True)
+                slot.cap["peaks_host"] = slot.bufs["peaks_host"].numel()
+        self._reserved = True
 
     def _launch(self, slot: _Slot):
         import torch
