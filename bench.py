@@ -43,13 +43,16 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def load_traffic(bytes_per_launch_alg: float):
-    """HBM bytes per launch from committed rocprofv3 PMC runs, if still current."""
+def load_traffic(workload: str):
+    """HBM bytes per launch from committed rocprofv3 PMC runs, if they were taken on
+    this workload and the kernel source has not changed since."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as f:
         t = json.load(f)
     if t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    if t.get("workload") != workload:
         return None
     return t.get("hbm_bytes_per_launch")
 
@@ -316,7 +319,7 @@ def main():
     flops_map = 2.0 * NP * wl.J * wl.F           # 2 N P J per frame (Eq. SRPapproxcompR)
     flops_gcc = 4.0 * NP * g.K * wl.F            # N P K complex MACs, real part (Eq. SRPapproxcompC)
     achieved = flops_map / (t_map * 1e-3) / 1e12
-    traffic = load_traffic(flops_map)
+    traffic = load_traffic(wl.name)
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                 "kernel": "nyquist_f32_kernel (srp_map_nyquist, FP32 MFMA 32x32x2)",
