@@ -166,7 +166,9 @@ srp_status srp_map_conventional(const srp_geometry_t* g, const float* psi, int32
  * integer and a float32 fraction.
  *   xi     device, F x S samples in the srp_gcc_samples layout, stored as
  *          float for SRP_FP32 and SRP_FP64, bfloat16 for SRP_BF16, half for
- *          SRP_FP16 (srp_gcc_samples with the same dtype writes them)
+ *          SRP_FP16 (srp_gcc_samples with the same dtype writes them); the gap
+ *          columns after each window must hold zeros, as that layout states
+ *          (the interpolation reads the first one with a weight, unmasked)
  *   dtype  SRP_FP32: float32 matrix cores; SRP_BF16 / SRP_FP16: weights and
  *          samples in that type on the matrix cores, float32 accumulation;
  *          SRP_FP64: float64 vector units (an exactness check, not a fast path)
