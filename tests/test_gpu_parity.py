@@ -358,3 +358,31 @@ def test_near_integer_tdoa_stays_finite(dtype):
                      frames=y)
     ref = R.oracle_nyquist(wl, R.oracle_xi(wl, R.oracle_psi(wl)), cand)
     assert _rel(got, ref).max() <= (MAP_TOL if dtype == "fp32" else LOWP_TOL)
+
+
+@pytest.fixture(scope="module")
+def many_frames():
+    # 520 frames: two full 256-frame blocks and a tail of 8
+    return WL.make_custom(M=5, J_shape=(10, 6, 5), L=256, F=520, seed=11)
+
+
+@pytest.mark.parametrize("F", [256, 257, 288, 500, 520])
+@pytest.mark.parametrize("dtype", ["fp32", "bf16", "fp16"])
+def test_nyquist_frame_block_boundaries(many_frames, F, dtype):
+    """Frame counts around the interpolation kernels' frame blocks (256 frames
+    per block, tail blocks of 1-7 32-frame tiles, a last block with fewer rows
+    than its tiles), against the oracle on the very samples the kernel read."""
+    wl = many_frames
+    g = _geom(wl)
+    fr = _frames(wl)[:F]
+    xi = srp.gcc_samples(g, srp.cross_spectra(g, fr), dtype=dtype)
+    m, pk = srp.map_nyquist(g, xi, dtype=dtype)
+    torch.cuda.synchronize()
+    xs = srp.unpack_samples(g, xi)
+    ref = R.oracle_nyquist(wl, xs, wl.candidates())
+    got = m.cpu().numpy().astype(np.float64)
+    assert got.shape == (F, wl.J) and np.all(np.isfinite(got))
+    assert _rel(got, ref).max() <= (MAP_TOL if dtype == "fp32" else LOWP_TOL)
+    idx, _ = srp.decode_peaks(pk)
+    np.testing.assert_array_equal(idx, np.argmax(got, axis=1))
+    R.check_argmax(idx, ref, MAP_TOL if dtype == "fp32" else LOWP_TOL)
