@@ -194,20 +194,46 @@ void cached_map_kernel(CachedArgs a, const T* __restrict__ xi, const T* __restri
     stage_tile<T, FB>(xblk, a.S, nrows, t * kCTile, a.S, a.zero, xb, wave, lane);
     stage_tile<T, JB>(wblk, a.Sw, jrows, t * kCTile, a.Sw, a.zero, wb, wave, lane);
   };
+  // Contraction of one staged tile (4 matrix-core steps of 16 columns),
+  // software-pipelined: the LDS operands of step s + 1 are read while the
+  // matrix cores work on step s (two operand sets), so the read latency is
+  // not exposed before every instruction.
   auto contract = [&](const T* xb, const T* wb) {
     const T* trow = xb + cl * kCRow;
     const T* wrow_l = wb + (wave * 32 + cl) * kCRow;
-#pragma unroll
-    for (int s = 0; s < kCSteps; ++s) {
+    vec8 a0[FT], a1[FT], b0, b1;
+    auto load = [&](int s, vec8 (&av)[FT], vec8& bw) {
       const int pc = (2 * s + g) ^ rowsw;
-      const vec8 bw = *reinterpret_cast<const vec8*>(wrow_l + 8 * pc);
-      vec8 av[FT];
+      bw = *reinterpret_cast<const vec8*>(wrow_l + 8 * pc);
 #pragma unroll
       for (int ft = 0; ft < FT; ++ft)
         av[ft] = *reinterpret_cast<const vec8*>(trow + ft * 32 * kCRow + 8 * pc);
+    };
+    auto mm = [&](const vec8 (&av)[FT], const vec8& bw) {
 #pragma unroll
       for (int ft = 0; ft < FT; ++ft) acc[ft] = Mx32<T>::mfma(av[ft], bw, acc[ft]);
-    }
+    };
+    auto order = [&]() {
+      // one matrix-core instruction, the next step's read addresses and LDS
+      // reads, then the remaining matrix-core instructions
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, FT + 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, FT - 1, 0);
+      __builtin_amdgcn_sched_barrier(0);  // one step per scheduling region
+    };
+    static_assert(kCSteps == 4, "the pipeline below is written for 4 steps per tile");
+    load(0, a0, b0);
+    load(1, a1, b1);
+    mm(a0, b0);
+    order();
+    load(2, a0, b0);
+    mm(a1, b1);
+    order();
+    load(3, a1, b1);
+    mm(a0, b0);
+    order();
+    mm(a1, b1);
   };
   // hand the buffers over: every copy has landed and the LDS reads of the
   // tile just contracted are done; a plain barrier (no memory fence)
