@@ -256,6 +256,26 @@ __device__ __forceinline__ V lag_weights(float base, float xf, float qs) {
   return v;
 }
 
+// The same weights when the sinc denominators are exact: tb = base + xf is a
+// float32 number and so is every tb - j (the fraction lies on a grid chosen
+// so), hence d_j = tb - j and d_{j+1} = d_j - 1 need no separate formation:
+// with u = d_j, r = qs / (u (u - 1)), w_j = (u - 1) r and w_{j+1} = -u r.
+template <typename T, typename V, int N>
+__device__ __forceinline__ V lag_weights_exact(float tb, float qs) {
+  float w[N];
+#pragma unroll
+  for (int j = 0; j < N; j += 2) {
+    const float u = tb - static_cast<float>(j);
+    const float r = qs * __builtin_amdgcn_rcpf(fmaf(u, u, -u));
+    w[j] = fmaf(r, u, -r);
+    w[j + 1] = -r * u;
+  }
+  V v;
+#pragma unroll
+  for (int j = 0; j < N; ++j) v[j] = static_cast<T>(w[j]);
+  return v;
+}
+
 // Lane layouts (64 lanes, g = lane / 16, c = lane % 16), result register r
 // holding D[4g + r][c] for both:
 //   v_mfma_f32_16x16x32: A[c][8g + j], B[8g + j][c], j = 0..7;
@@ -287,6 +307,7 @@ __global__ __launch_bounds__(256) void nyquist_batched_mx_kernel(
   floatx4 acc[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) acc[t] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+  const double xq_scale = ldexp(1.0, it.xq_exp);
   int cur_m = -1;
   double rm = 0.0;
   for (int p = 0; p < it.P; ++p) {
@@ -308,9 +329,15 @@ __global__ __launch_bounds__(256) void nyquist_batched_mx_kernel(
       }
       x = (rm - norm3(qx - pn[0], qy - pn[1], qz - pn[2])) * it.inv_cT;
     }
+    // the fraction rounded to the grid 2^-xq_exp (a nonzero grid point), so
+    // that the sinc denominators below are exact float32 numbers; this moves
+    // x by at most half a grid step (2^-17 for the serving arrays), a change
+    // of the weights far below a BF16/FP16 unit
     const double r = rint(x);
     double fd = x - r;
-    fd = fabs(fd) < 1e-30 ? 1e-30 : fd;
+    double q = rint(fd * xq_scale);
+    q = q != 0.0 ? q : (fd < 0.0 ? -1.0 : 1.0);
+    fd = q / xq_scale;
     const int xr_own = static_cast<int>(r);
     const float xf_own = static_cast<float>(fd);
     const float sp_own = sinpi_over_pi(fd);
@@ -345,7 +372,7 @@ __global__ __launch_bounds__(256) void nyquist_batched_mx_kernel(
         const int base = ia[t] - t0;
         const float qs = (base & 1) ? -sp[t] : sp[t];
         acc[t] = Mx16<T>::mfma(
-            av, lag_weights<T, vec8, 8>(static_cast<float>(base), xf[t], qs), acc[t]);
+            av, lag_weights_exact<T, vec8, 8>(static_cast<float>(base) + xf[t], qs), acc[t]);
       }
     }
     if (rem > 0 && rem <= 16) {
@@ -362,7 +389,7 @@ __global__ __launch_bounds__(256) void nyquist_batched_mx_kernel(
         const int base = ia[t] - t0;
         const float qs = (base & 1) ? -sp[t] : sp[t];
         acc[t] = Mx16<T>::mfma16(
-            av, lag_weights<T, vec4, 4>(static_cast<float>(base), xf[t], qs), acc[t]);
+            av, lag_weights_exact<T, vec4, 4>(static_cast<float>(base) + xf[t], qs), acc[t]);
       }
     }
   }

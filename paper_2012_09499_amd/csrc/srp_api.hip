@@ -550,7 +550,17 @@ srp_status srp_map_nyquist_batched(const srp_batch_item* items, int32_t n_items,
       d.map = it.map;
       d.keys = reinterpret_cast<unsigned long long*>(it.peaks);
       d.block_begin = static_cast<int>(blocks[grp]);
-      d.pad = 0;
+      // matrix-core items: the grid 2^-e of the TDOA fractions on which every
+      // sinc denominator (|d| < 2 h_max + 64) is a float32 number
+      d.xq_exp = 0;
+      if (grp == 1) {
+        int hmax = 0;
+        for (const PairDesc& pd : it.g->pairs) hmax = pd.h > hmax ? pd.h : hmax;
+        int bits = 0;
+        while ((int64_t(1) << bits) <= 2 * int64_t(hmax) + 64) ++bits;
+        d.xq_exp = 24 - bits;
+        if (d.xq_exp < 8) return fail(SRP_ERR_UNSUPPORTED, "pair windows too long for BF16/FP16 batches");
+      }
       dev.push_back(d);
       blocks[grp] += (d.J + 255) / 256;
       ++n_group[grp];

@@ -66,7 +66,7 @@ struct BatchItemDev {
   float* map;                // [F][J] or null
   unsigned long long* keys;  // srp_peak[F] viewed as u64 pairs, or null
   int block_begin;           // first workgroup of the item
-  int pad;
+  int xq_exp;                // matrix-core items: fractions on the grid 2^-xq_exp (see k_batched)
 };
 
 }  // namespace srp
