@@ -244,10 +244,14 @@ srp_status srp_map_nyquist_batched_workspace(int32_t n_items, size_t* bytes);
  *              frames per array the weights are formed once per candidate and
  *              lag and used by those frames only), the accuracy of
  *              srp_map_nyquist in FP32;
- *              SRP_BF16 / SRP_FP16: weights in that type on the matrix cores
- *              (16 frames x 16 candidates x 32 lags per instruction), float32
- *              accumulation, the accuracy of srp_map_nyquist in that type; the
- *              arena must be 16-byte aligned and every xi_offset a multiple of 8
+ *              SRP_BF16 / SRP_FP16: items of one or two frames on the vector
+ *              units, longer ones on the matrix cores (16 frames x 16
+ *              candidates x 32 lags per instruction); weights in that type,
+ *              float32 accumulation, the TDOA fraction rounded to a grid of at
+ *              most 2^-8 (2^-16 for windows of up to 191 lags) on which every
+ *              sinc denominator is exact; the accuracy of srp_map_nyquist in
+ *              that type; the arena must be 16-byte aligned and every
+ *              xi_offset a multiple of 8
  *   workspace  device, >= srp_map_nyquist_batched_workspace bytes; holds the
  *              item table until the launch has finished (do not reuse it for
  *              another batch on another stream before then)

@@ -25,6 +25,8 @@
 //
 // Workgroup b belongs to the item whose [block_begin, block_begin + blocks)
 // range contains b (binary search over the item table).
+#include <type_traits>
+
 #include "srp_device.h"
 #include "srp_internal.h"
 
@@ -98,6 +100,8 @@ __global__ __launch_bounds__(256) void nyquist_batched_kernel(const BatchItemDev
   const int64_t ci0 = (int64_t)(b - it.block_begin) * 256 + threadIdx.x;
   const int64_t ci = ci0 < it.J ? ci0 : it.J - 1;
   const double qx = it.cand[ci], qy = it.cand[it.J + ci], qz = it.cand[2 * it.J + ci];
+  constexpr bool kExact = !std::is_same<T, float>::value;
+  const double xq_scale = ldexp(1.0, it.xq_exp);
 
   float tot[FMAX];
 #pragma unroll
@@ -127,7 +131,16 @@ __global__ __launch_bounds__(256) void nyquist_batched_kernel(const BatchItemDev
     }
     const double r = rint(x);
     double fd = x - r;
-    fd = fabs(fd) < 1e-30 ? 1e-30 : fd;
+    if (kExact) {
+      // BF16/FP16 items: the fraction on the grid 2^-xq_exp (a nonzero grid
+      // point), so that every sinc denominator below is an exact float32
+      // number (see nyquist_batched_mx_kernel)
+      double q = rint(fd * xq_scale);
+      q = q != 0.0 ? q : (fd < 0.0 ? -1.0 : 1.0);
+      fd = q / xq_scale;
+    } else {
+      fd = fabs(fd) < 1e-30 ? 1e-30 : fd;
+    }
     const float xf = static_cast<float>(fd);
     const float sp = sinpi_over_pi(fd);
     // lag t = 0 .. 2h: n = t - h, x - n = (xr + h - t) + xf
@@ -143,7 +156,24 @@ __global__ __launch_bounds__(256) void nyquist_batched_kernel(const BatchItemDev
     for (int f = 0; f < FMAX; ++f)
       row[f] = xi + it.xi_off + (size_t)(f < it.F ? f : it.F - 1) * it.S + pd.off;
     const int W = 2 * pd.h + 1;
-    float base = static_cast<float>(ia);
+    // the weights of lags t and t + 1 from one reciprocal: d0 = base + xf,
+    // d1 = d0 - 1 (base = ia - t), r = q0 / (d0 d1), w0 = d1 r, w1 = -d0 r;
+    // FP32 items form each denominator as (exact integer) + xf, BF16/FP16
+    // items hold the exact sum base + xf in `base`
+    auto pair_weights = [&](float b, float& w0, float& w1) {
+      if (kExact) {
+        const float qr = q0 * __builtin_amdgcn_rcpf(fmaf(b, b, -b));
+        w0 = fmaf(qr, b, -qr);
+        w1 = -qr * b;
+      } else {
+        const float d0 = b + xf;
+        const float d1 = (b - 1.0f) + xf;
+        const float qr = q0 * __builtin_amdgcn_rcpf(d0 * d1);
+        w0 = qr * d1;
+        w1 = -qr * d0;
+      }
+    };
+    float base = static_cast<float>(ia) + (kExact ? xf : 0.0f);
     int t = 0;
     // 8 lags per iteration: each frame's 8 samples arrive by one scalar load,
     // issued together before the arithmetic that uses them
@@ -153,11 +183,8 @@ __global__ __launch_bounds__(256) void nyquist_batched_kernel(const BatchItemDev
       for (int f = 0; f < FMAX; ++f) load8(row[f] + t, xs[f]);
 #pragma unroll
       for (int j = 0; j < 8; j += 2, base -= 2.0f) {
-        const float d0 = base + xf;
-        const float d1 = (base - 1.0f) + xf;
-        const float qr = q0 * __builtin_amdgcn_rcpf(d0 * d1);
-        const float w0 = qr * d1;
-        const float w1 = -qr * d0;
+        float w0, w1;
+        pair_weights(base, w0, w1);
 #pragma unroll
         for (int f = 0; f < FMAX; ++f) {
           acc[f] = fmaf(w0, xs[f][j], acc[f]);
@@ -166,11 +193,8 @@ __global__ __launch_bounds__(256) void nyquist_batched_kernel(const BatchItemDev
       }
     }
     for (; t + 1 < W; t += 2, base -= 2.0f) {
-      const float d0 = base + xf;
-      const float d1 = (base - 1.0f) + xf;
-      const float qr = q0 * __builtin_amdgcn_rcpf(d0 * d1);
-      const float w0 = qr * d1;
-      const float w1 = -qr * d0;
+      float w0, w1;
+      pair_weights(base, w0, w1);
 #pragma unroll
       for (int f = 0; f < FMAX; ++f) {
         float x0, x1;
@@ -180,7 +204,7 @@ __global__ __launch_bounds__(256) void nyquist_batched_kernel(const BatchItemDev
       }
     }
     {  // last lag (W is odd)
-      const float w0 = q0 * __builtin_amdgcn_rcpf(base + xf);
+      const float w0 = q0 * __builtin_amdgcn_rcpf(kExact ? base : base + xf);
 #pragma unroll
       for (int f = 0; f < FMAX; ++f) {
         float x0, x1;  // x1 is the first zero of the window's padding
@@ -467,8 +491,6 @@ hipError_t launch_nyquist_batched(const BatchItemDev* d_items, int n_vec, int bl
       const __bf16* x = static_cast<const __bf16*>(xi);
       if (max_f_vec <= 1)
         hipLaunchKernelGGL((nyquist_batched_kernel<1, __bf16>), grid, blk, 0, s, d_items, n_vec, x);
-      else if (max_f_vec <= 2)
-        hipLaunchKernelGGL((nyquist_batched_kernel<2, __bf16>), grid, blk, 0, s, d_items, n_vec, x);
       else
         hipLaunchKernelGGL((nyquist_batched_kernel<kBatchVecMaxF, __bf16>), grid, blk, 0, s,
                            d_items, n_vec, x);
@@ -476,9 +498,6 @@ hipError_t launch_nyquist_batched(const BatchItemDev* d_items, int n_vec, int bl
       const _Float16* x = static_cast<const _Float16*>(xi);
       if (max_f_vec <= 1)
         hipLaunchKernelGGL((nyquist_batched_kernel<1, _Float16>), grid, blk, 0, s, d_items, n_vec,
-                           x);
-      else if (max_f_vec <= 2)
-        hipLaunchKernelGGL((nyquist_batched_kernel<2, _Float16>), grid, blk, 0, s, d_items, n_vec,
                            x);
       else
         hipLaunchKernelGGL((nyquist_batched_kernel<kBatchVecMaxF, _Float16>), grid, blk, 0, s,

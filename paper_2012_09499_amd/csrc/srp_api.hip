@@ -550,10 +550,10 @@ srp_status srp_map_nyquist_batched(const srp_batch_item* items, int32_t n_items,
       d.map = it.map;
       d.keys = reinterpret_cast<unsigned long long*>(it.peaks);
       d.block_begin = static_cast<int>(blocks[grp]);
-      // matrix-core items: the grid 2^-e of the TDOA fractions on which every
+      // BF16/FP16 items: the grid 2^-e of the TDOA fractions on which every
       // sinc denominator (|d| < 2 h_max + 64) is a float32 number
       d.xq_exp = 0;
-      if (grp == 1) {
+      if (mx) {
         int hmax = 0;
         for (const PairDesc& pd : it.g->pairs) hmax = pd.h > hmax ? pd.h : hmax;
         int bits = 0;

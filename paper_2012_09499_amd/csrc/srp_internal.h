@@ -50,9 +50,9 @@ constexpr int kGccLagTile = 32;
 constexpr int kBatchMaxF = 8;
 constexpr int kBatchMaxFMx = 16;
 // BF16/FP16 items with at most this many frames run on the vector units (the
-// matrix-core tile costs the same for 1 and for 16 frames; measured over 64
-// serving arrays, the vector kernel is faster up to 4 frames per array).
-constexpr int kBatchVecMaxF = 4;
+// matrix-core tile costs about the same for 1 and for 16 frames; measured over
+// 64 serving arrays, the vector kernel is faster up to 2 frames per array).
+constexpr int kBatchVecMaxF = 2;
 
 // Device copy of one item of a batched launch.
 struct BatchItemDev {
@@ -66,7 +66,7 @@ struct BatchItemDev {
   float* map;                // [F][J] or null
   unsigned long long* keys;  // srp_peak[F] viewed as u64 pairs, or null
   int block_begin;           // first workgroup of the item
-  int xq_exp;                // matrix-core items: fractions on the grid 2^-xq_exp (see k_batched)
+  int xq_exp;                // BF16/FP16 items: fractions on the grid 2^-xq_exp (see k_batched)
 };
 
 }  // namespace srp
