@@ -11,10 +11,12 @@
 //
 // The map is then the plain product map[f][i] = 2 sum_k W[i][k] xi[f][k]
 // over the packed columns: no TDOA and no weight arithmetic per frame batch.
-// It runs on v_mfma_f32_32x32x16_{bf16,f16} with the same tiling as the
-// on-the-fly kernel (workgroup = 8 waves x 32 candidates, 256 frames; samples
-// staged in 64-column tiles through LDS with a conflict-free swizzle); the
-// weights of the workgroup's 256 candidates are staged the same way (rows of
+// It runs on v_mfma_f32_32x32x16_{bf16,f16}: workgroup = 256 candidates x
+// 256 frames, each of its 8 waves 64 candidates x 128 frames (both operands
+// come from LDS here, and this square-ish wave tile reads 6 operand chunks per
+// 8 matrix-core instructions, against 9 for 32 candidates x 256 frames);
+// samples staged in 64-column tiles through LDS with a conflict-free swizzle;
+// the weights of the workgroup's 256 candidates are staged the same way (rows of
 // W are 16-byte chunks apart in the operand layout, so direct loads would
 // fetch each cache line several times); copies run one tile ahead. The frame blocks of a
 // candidate tile are placed on the same XCD at the same time (workgroup b
@@ -100,8 +102,12 @@ __global__ __launch_bounds__(256) void weights_kernel(
 }
 
 // ---------------------------------------------------------------- map
-constexpr int kCWaves = 8;     // waves per workgroup (32 candidates each)
+constexpr int kCWaves = 8;     // waves per workgroup
 constexpr int kCFT = 8;        // 32-frame tiles per workgroup
+constexpr int kCWC = 4;        // waves along the candidates (x kCWF along the frames)
+constexpr int kCWF = kCWaves / kCWC;
+constexpr int kCCT = 2;        // 32-candidate tiles per wave
+constexpr int kCWT = kCFT / kCWF;  // 32-frame tiles per wave
 constexpr int kCTile = 64;     // packed columns per staged tile
 constexpr int kCRow = kCTile;  // LDS row length (elements, 128 bytes)
 constexpr int kCSteps = kCTile / 16;  // matrix-core steps per tile
@@ -168,21 +174,25 @@ void cached_map_kernel(CachedArgs a, const T* __restrict__ xi, const T* __restri
   const int lane = tid & 63;
   const int cl = lane & 31;
   const int g = lane >> 5;
-  const int64_t jb = (int64_t)ct * JB + wave * 32;
+  static_assert(JB == 32 * kCCT * kCWC && FT == kCWT * kCWF, "wave tiles cover the workgroup");
+  const int wc = wave % kCWC;  // the wave's candidate rows: 64 wc .. 64 wc + 63
+  const int wf = wave / kCWC;  // the wave's frame rows: 128 wf .. 128 wf + 127
+  const int64_t jb = (int64_t)ct * JB + wc * 32 * kCCT;
   const int f0 = fb * FB;
   const int nrows = a.F - f0 < FB ? a.F - f0 : FB;
-  const int64_t ci = jb + cl;
   const int64_t j0 = (int64_t)ct * JB;           // first candidate of the workgroup
   const int jrows = a.J - j0 < JB ? static_cast<int>(a.J - j0) : JB;
   const T* wblk = w + j0 * a.Sw;
   const T* xblk = xi + (size_t)f0 * a.S;
   for (int i = tid; i < FB; i += 64 * kCWaves) kbest[i] = 0ull;
 
-  floatx16 acc[FT];
+  floatx16 acc[kCCT][kCWT];
 #pragma unroll
-  for (int ft = 0; ft < FT; ++ft)
+  for (int c = 0; c < kCCT; ++c)
 #pragma unroll
-    for (int k = 0; k < 16; ++k) acc[ft][k] = 0.0f;
+    for (int ft = 0; ft < kCWT; ++ft)
+#pragma unroll
+      for (int k = 0; k < 16; ++k) acc[c][ft][k] = 0.0f;
 
   // Two buffers each for the sample tile [256 frames][64 columns] and the
   // weight tile [256 candidates][64 columns], both copied with coalesced
@@ -199,27 +209,31 @@ void cached_map_kernel(CachedArgs a, const T* __restrict__ xi, const T* __restri
   // matrix cores work on step s (two operand sets), so the read latency is
   // not exposed before every instruction.
   auto contract = [&](const T* xb, const T* wb) {
-    const T* trow = xb + cl * kCRow;
-    const T* wrow_l = wb + (wave * 32 + cl) * kCRow;
-    vec8 a0[FT], a1[FT], b0, b1;
-    auto load = [&](int s, vec8 (&av)[FT], vec8& bw) {
+    const T* trow = xb + (wf * 32 * kCWT + cl) * kCRow;
+    const T* wrow = wb + (wc * 32 * kCCT + cl) * kCRow;
+    vec8 a0[kCWT], a1[kCWT], b0[kCCT], b1[kCCT];
+    auto load = [&](int s, vec8 (&av)[kCWT], vec8 (&bw)[kCCT]) {
       const int pc = (2 * s + g) ^ rowsw;
-      bw = *reinterpret_cast<const vec8*>(wrow_l + 8 * pc);
 #pragma unroll
-      for (int ft = 0; ft < FT; ++ft)
+      for (int c = 0; c < kCCT; ++c)
+        bw[c] = *reinterpret_cast<const vec8*>(wrow + c * 32 * kCRow + 8 * pc);
+#pragma unroll
+      for (int ft = 0; ft < kCWT; ++ft)
         av[ft] = *reinterpret_cast<const vec8*>(trow + ft * 32 * kCRow + 8 * pc);
     };
-    auto mm = [&](const vec8 (&av)[FT], const vec8& bw) {
+    auto mm = [&](const vec8 (&av)[kCWT], const vec8 (&bw)[kCCT]) {
 #pragma unroll
-      for (int ft = 0; ft < FT; ++ft) acc[ft] = Mx32<T>::mfma(av[ft], bw, acc[ft]);
+      for (int c = 0; c < kCCT; ++c)
+#pragma unroll
+        for (int ft = 0; ft < kCWT; ++ft) acc[c][ft] = Mx32<T>::mfma(av[ft], bw[c], acc[c][ft]);
     };
     auto order = [&]() {
       // one matrix-core instruction, the next step's read addresses and LDS
       // reads, then the remaining matrix-core instructions
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
       __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
-      __builtin_amdgcn_sched_group_barrier(0x100, FT + 1, 0);
-      __builtin_amdgcn_sched_group_barrier(0x008, FT - 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, kCWT + kCCT, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, kCCT * kCWT - 1, 0);
       __builtin_amdgcn_sched_barrier(0);  // one step per scheduling region
     };
     static_assert(kCSteps == 4, "the pipeline below is written for 4 steps per tile");
@@ -257,16 +271,21 @@ void cached_map_kernel(CachedArgs a, const T* __restrict__ xi, const T* __restri
   // epilogue: x2, optional map store, argmax (LDS max per frame, then one
   // global 64-bit atomic per frame and workgroup)
 #pragma unroll
-  for (int ft = 0; ft < FT; ++ft) {
+  for (int ft = 0; ft < kCWT; ++ft) {
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-      const int fl = ft * 32 + 8 * (k >> 2) + 4 * g + (k & 3);
+      const int fl = (wf * kCWT + ft) * 32 + 8 * (k >> 2) + 4 * g + (k & 3);
       const int fg = f0 + fl;
       unsigned long long best = 0ull;
-      const float v = 2.0f * acc[ft][k];
-      if (ci < a.J && fg < a.F) {
-        if (a.map) a.map[(size_t)fg * a.J + ci] = v;
-        best = peak_key(v, static_cast<unsigned>(ci));
+#pragma unroll
+      for (int c = 0; c < kCCT; ++c) {
+        const int64_t ci = jb + c * 32 + cl;
+        const float v = 2.0f * acc[c][ft][k];
+        if (ci < a.J && fg < a.F) {
+          if (a.map) a.map[(size_t)fg * a.J + ci] = v;
+          const unsigned long long key = peak_key(v, static_cast<unsigned>(ci));
+          best = key > best ? key : best;
+        }
       }
       if (a.keys) {
         best = half_wave_max(best);
