@@ -21,7 +21,8 @@
 // exists anywhere.
 //
 // FP32 kernel layout (v_mfma_f32_32x32x2f32, D[frame][cand] += A[frame][k] B[k][cand]):
-//   block = 4 waves; each wave owns 32 * CT candidates, all waves share 32 * FT frames;
+//   block = NW waves (8; 4 for the two-level sum), two per SIMD; each wave owns
+//   32 * CT candidates, all waves share the block's 32 * FT frames;
 //   step s of a lag run covers lags t = 2s (k = 0, lanes 0-31) and 2s + 1 (k = 1, lanes 32-63);
 //   A = samples staged in LDS as [frame][lag]; B = weights (lane = candidate);
 //   epilogue: x2, optional map store, argmax via LDS u64 max + one global atomic per frame.
