@@ -51,6 +51,7 @@ struct NyqArgs {
   const float* xi;         // [F][S]
   int F;
   int f_base;              // first frame of this launch's frame blocks
+  int64_t j_base;          // first candidate of this launch's candidate blocks
   int S;
   int64_t J;
   double inv_cT;
@@ -324,7 +325,7 @@ void nyquist_f32_kernel(NyqArgs a, const RunRec* __restrict__ recs) {
   const int lane = tid & 63;
   const int cl = lane & 31;
   const int g = lane >> 5;
-  const int64_t jb = (int64_t)blockIdx.x * JB + wave * JW;
+  const int64_t jb = a.j_base + (int64_t)blockIdx.x * JB + wave * JW;
   const int f0 = a.f_base + blockIdx.y * FB;
   const int nrows = a.F - f0 < FB ? a.F - f0 : FB;
 
@@ -613,7 +614,7 @@ void nyquist_mx_kernel(NyqArgs a, const T* __restrict__ xi, const RunRec* __rest
   const int lane = tid & 63;
   const int cl = lane & 31;
   const int g = lane >> 5;
-  const int64_t jb = (int64_t)blockIdx.x * JB + wave * 32;
+  const int64_t jb = a.j_base + (int64_t)blockIdx.x * JB + wave * 32;
   const int f0 = a.f_base + blockIdx.y * FB;
   const int nrows = a.F - f0 < FB ? a.F - f0 : FB;
 
@@ -782,6 +783,45 @@ void launch_frame_blocks(int F, const NyqArgs& a, Launch&& launch) {
   }
 }
 
+// Launches of a kernel with 256-candidate blocks, per_cu workgroups per CU at
+// a time (as their LDS and registers allow) and all of about the same
+// duration. When the workgroups do not fill a whole number of rounds of the
+// CUs, the last round would leave CUs idle for a whole workgroup's time. So the candidate blocks that fill whole
+// rounds run first (frame blocks of 8 tiles), and the rest run in one launch
+// with the shortest frame blocks that fit in one round (its
+// last frame block carries padding rows rather than becoming a launch of its
+// own, which would be another round). launch(ft, args, grid) launches the
+// kernel instance with ft 32-frame tiles per block.
+template <typename Launch>
+void launch_in_rounds(const srp_geometry_s* g, int F, const NyqArgs& a, int per_cu,
+                      Launch&& launch) {
+  constexpr int JB = 256;
+  const int64_t round = (int64_t)g->n_cu * per_cu;
+  const int64_t n_cb = (a.J + JB - 1) / JB;
+  const int64_t n_fb = (F + 255) / 256;
+  const int64_t full_cb = (n_cb * n_fb) / round * round / n_fb;
+  const int64_t rest_cb = n_cb - full_cb;
+  auto rest_fb = [&](int ft) { return (F + 32 * ft - 1) / (32 * ft); };
+  int ft_rest = 0;
+  for (int ft = 4; ft <= 7 && ft_rest == 0; ++ft)
+    if (rest_cb * rest_fb(ft) <= round) ft_rest = ft;
+  const bool split = full_cb > 0 && rest_cb > 0 && ft_rest > 0;
+  const unsigned gx = static_cast<unsigned>(split ? full_cb : n_cb);
+  launch_frame_blocks<8>(F, a, [&](auto ft, const NyqArgs& b, int fblocks) {
+    launch(ft, b, dim3(gx, fblocks));
+  });
+  if (!split) return;
+  NyqArgs b = a;
+  b.j_base = full_cb * JB;
+  const dim3 grid(static_cast<unsigned>(rest_cb), static_cast<unsigned>(rest_fb(ft_rest)));
+  switch (ft_rest) {
+    case 4: launch(std::integral_constant<int, 4>(), b, grid); break;
+    case 5: launch(std::integral_constant<int, 5>(), b, grid); break;
+    case 6: launch(std::integral_constant<int, 6>(), b, grid); break;
+    default: launch(std::integral_constant<int, 7>(), b, grid); break;
+  }
+}
+
 hipError_t launch_nyquist(const srp_geometry_s* g, const void* xi, int F, int dtype, float* map,
                           unsigned long long* keys, hipStream_t s) {
   NyqArgs a;
@@ -793,6 +833,7 @@ hipError_t launch_nyquist(const srp_geometry_s* g, const void* xi, int F, int dt
   a.xi = static_cast<const float*>(xi);
   a.F = F;
   a.f_base = 0;
+  a.j_base = 0;
   a.S = static_cast<int>(g->info.S);
   a.J = g->info.J;
   a.inv_cT = g->inv_cT;
@@ -803,26 +844,27 @@ hipError_t launch_nyquist(const srp_geometry_s* g, const void* xi, int F, int dt
   if (dtype == SRP_FP32) {
     int64_t samples = 0;
     for (const PairDesc& pd : g->pairs) samples += 2 * pd.h + 1;
-    if (samples <= kNyqPlainSumMax)
-      launch_frame_blocks<8>(F, a, [&](auto ft, const NyqArgs& b, int fblocks) {
-        constexpr int CT = 1, NW = 8, JB = NW * 32 * CT;
-        const dim3 grid(static_cast<unsigned>((b.J + JB - 1) / JB), fblocks);
-        hipLaunchKernelGGL((nyquist_f32_kernel<CT, decltype(ft)::value, NW, false>), grid,
-                           dim3(64 * NW), 0, s, b, g->d_nyq_recs);
+    if (samples <= kNyqPlainSumMax) {
+      // one workgroup per CU (130 KB of LDS)
+      launch_in_rounds(g, F, a, 1, [&](auto ft, const NyqArgs& b, dim3 grid) {
+        hipLaunchKernelGGL((nyquist_f32_kernel<1, decltype(ft)::value, 8, false>), grid,
+                           dim3(64 * 8), 0, s, b, g->d_nyq_recs);
       });
-    else
+    } else {
       launch_frame_blocks<4>(F, a, [&](auto ft, const NyqArgs& b, int fblocks) {
         constexpr int CT = 1, NW = 4, JB = NW * 32 * CT;
         const dim3 grid(static_cast<unsigned>((b.J + JB - 1) / JB), fblocks);
         hipLaunchKernelGGL((nyquist_f32_kernel<CT, decltype(ft)::value, NW, true>), grid,
                            dim3(64 * NW), 0, s, b, g->d_nyq_recs);
       });
+    }
     return hipGetLastError();
   }
   if (dtype == SRP_BF16 || dtype == SRP_FP16) {
-    launch_frame_blocks<8>(F, a, [&](auto ft, const NyqArgs& b, int fblocks) {
-      constexpr int JB = kMxWaves * 32;
-      const dim3 grid(static_cast<unsigned>((b.J + JB - 1) / JB), fblocks), blk(64 * kMxWaves);
+    static_assert(kMxWaves * 32 == 256, "256-candidate blocks");
+    // two workgroups per CU (66 KB of LDS, 124 registers per lane)
+    launch_in_rounds(g, F, a, 2, [&](auto ft, const NyqArgs& b, dim3 grid) {
+      const dim3 blk(64 * kMxWaves);
       if (dtype == SRP_BF16)
         hipLaunchKernelGGL((nyquist_mx_kernel<__bf16, decltype(ft)::value>), grid, blk, 0, s, b,
                            static_cast<const __bf16*>(xi), g->d_nyq_recs);

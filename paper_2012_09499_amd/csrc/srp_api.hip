@@ -275,6 +275,9 @@ srp_status srp_geometry(const double* mic_xyz, int32_t M, const double* cand_xyz
 
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = hipGetDevice(&g->device);
+  if (e == hipSuccess)
+    e = hipDeviceGetAttribute(&g->n_cu, hipDeviceAttributeMultiprocessorCount, g->device);
+  if (e == hipSuccess && g->n_cu < 1) g->n_cu = 1;
   if (e == hipSuccess) e = upload(&g->d_mic, mic_xyz, 3 * (size_t)M, s);
   if (e == hipSuccess) e = upload(&g->d_cand, cand_soa.data(), cand_soa.size(), s);
   if (e == hipSuccess) e = upload(&g->d_pairs, g->pairs.data(), g->pairs.size(), s);

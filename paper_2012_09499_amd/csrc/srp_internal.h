@@ -74,6 +74,7 @@ struct BatchItemDev {
 struct srp_geometry_s {
   srp_geometry_info info;
   int device = 0;
+  int n_cu = 256;          // compute units of the device (workgroup rounds)
   double inv_cT = 0.0;     // converts a path difference in metres into x = dt / T
   double fs_over_c = 0.0;  // converts a path difference in metres into samples
   int log2L = 0;
