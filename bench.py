@@ -322,7 +322,9 @@ def main():
     traffic = load_traffic(wl.name)
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
-                "kernel": "nyquist_f32_kernel (srp_map_nyquist, FP32 MFMA 32x32x2)",
+                "kernel": "nyquist_f32_kernel (srp_map_nyquist, FP32 MFMA 32x32x2; one launch "
+                          "of 8-tile frame blocks and, where they leave a partial round of the "
+                          "CUs, one of shorter blocks; timed together per call)",
                 "algorithmic_flops_per_launch": flops_map,
                 "avg_launch_ms": t_map}
 
