@@ -822,6 +822,21 @@ void launch_in_rounds(const srp_geometry_s* g, int F, const NyqArgs& a, int per_
   }
 }
 
+int nyquist_workgroups_per_cu(int dtype) {
+  int n = 0;
+  hipError_t e;
+  if (dtype == SRP_FP32)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &n, reinterpret_cast<const void*>(&nyquist_f32_kernel<1, 8, 8, false>), 64 * 8, 0);
+  else if (dtype == SRP_BF16)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &n, reinterpret_cast<const void*>(&nyquist_mx_kernel<__bf16, 8>), 64 * kMxWaves, 0);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &n, reinterpret_cast<const void*>(&nyquist_mx_kernel<_Float16, 8>), 64 * kMxWaves, 0);
+  return e == hipSuccess && n > 0 ? n : 1;
+}
+
 hipError_t launch_nyquist(const srp_geometry_s* g, const void* xi, int F, int dtype, float* map,
                           unsigned long long* keys, hipStream_t s) {
   NyqArgs a;
@@ -845,8 +860,7 @@ hipError_t launch_nyquist(const srp_geometry_s* g, const void* xi, int F, int dt
     int64_t samples = 0;
     for (const PairDesc& pd : g->pairs) samples += 2 * pd.h + 1;
     if (samples <= kNyqPlainSumMax) {
-      // one workgroup per CU (130 KB of LDS)
-      launch_in_rounds(g, F, a, 1, [&](auto ft, const NyqArgs& b, dim3 grid) {
+      launch_in_rounds(g, F, a, g->wg_per_cu[0], [&](auto ft, const NyqArgs& b, dim3 grid) {
         hipLaunchKernelGGL((nyquist_f32_kernel<1, decltype(ft)::value, 8, false>), grid,
                            dim3(64 * 8), 0, s, b, g->d_nyq_recs);
       });
@@ -862,8 +876,8 @@ hipError_t launch_nyquist(const srp_geometry_s* g, const void* xi, int F, int dt
   }
   if (dtype == SRP_BF16 || dtype == SRP_FP16) {
     static_assert(kMxWaves * 32 == 256, "256-candidate blocks");
-    // two workgroups per CU (66 KB of LDS, 124 registers per lane)
-    launch_in_rounds(g, F, a, 2, [&](auto ft, const NyqArgs& b, dim3 grid) {
+    const int per_cu = g->wg_per_cu[dtype == SRP_BF16 ? 1 : 2];
+    launch_in_rounds(g, F, a, per_cu, [&](auto ft, const NyqArgs& b, dim3 grid) {
       const dim3 blk(64 * kMxWaves);
       if (dtype == SRP_BF16)
         hipLaunchKernelGGL((nyquist_mx_kernel<__bf16, decltype(ft)::value>), grid, blk, 0, s, b,

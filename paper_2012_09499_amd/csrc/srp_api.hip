@@ -278,6 +278,11 @@ srp_status srp_geometry(const double* mic_xyz, int32_t M, const double* cand_xyz
   if (e == hipSuccess)
     e = hipDeviceGetAttribute(&g->n_cu, hipDeviceAttributeMultiprocessorCount, g->device);
   if (e == hipSuccess && g->n_cu < 1) g->n_cu = 1;
+  if (e == hipSuccess) {
+    g->wg_per_cu[0] = nyquist_workgroups_per_cu(SRP_FP32);
+    g->wg_per_cu[1] = nyquist_workgroups_per_cu(SRP_BF16);
+    g->wg_per_cu[2] = nyquist_workgroups_per_cu(SRP_FP16);
+  }
   if (e == hipSuccess) e = upload(&g->d_mic, mic_xyz, 3 * (size_t)M, s);
   if (e == hipSuccess) e = upload(&g->d_cand, cand_soa.data(), cand_soa.size(), s);
   if (e == hipSuccess) e = upload(&g->d_pairs, g->pairs.data(), g->pairs.size(), s);

@@ -75,6 +75,7 @@ struct srp_geometry_s {
   srp_geometry_info info;
   int device = 0;
   int n_cu = 256;          // compute units of the device (workgroup rounds)
+  int wg_per_cu[3] = {1, 1, 1};  // resident Nyquist workgroups per CU: FP32, BF16, FP16
   double inv_cT = 0.0;     // converts a path difference in metres into x = dt / T
   double fs_over_c = 0.0;  // converts a path difference in metres into samples
   int log2L = 0;
@@ -113,6 +114,7 @@ hipError_t launch_cross(const srp_geometry_s* g, const float2* ytil, int F, floa
                         hipStream_t s);
 hipError_t launch_gcc_samples(const srp_geometry_s* g, const float2* psi, int F, int dtype,
                               void* xi, hipStream_t s);
+int nyquist_workgroups_per_cu(int dtype);  // occupancy of the interpolation kernels
 hipError_t launch_nyquist(const srp_geometry_s* g, const void* xi, int F, int dtype, float* map,
                           unsigned long long* keys, hipStream_t s);
 hipError_t launch_conventional(const srp_geometry_s* g, const float2* psi, int F, int dtype,
