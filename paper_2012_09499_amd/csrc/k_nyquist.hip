@@ -786,12 +786,13 @@ void launch_frame_blocks(int F, const NyqArgs& a, Launch&& launch) {
 // Launches of a kernel with 256-candidate blocks, per_cu workgroups per CU at
 // a time (as their LDS and registers allow) and all of about the same
 // duration. When the workgroups do not fill a whole number of rounds of the
-// CUs, the last round would leave CUs idle for a whole workgroup's time. So the candidate blocks that fill whole
-// rounds run first (frame blocks of 8 tiles), and the rest run in one launch
-// with the shortest frame blocks that fit in one round (its
-// last frame block carries padding rows rather than becoming a launch of its
-// own, which would be another round). launch(ft, args, grid) launches the
-// kernel instance with ft 32-frame tiles per block.
+// CUs, the last round would leave CUs idle for a whole workgroup's time. So
+// the candidate blocks that fill whole rounds run first (frame blocks of up to
+// 8 tiles), and the rest run in one launch with the shortest frame blocks of
+// which one round holds them all, if those are shorter than the first
+// launch's (their last frame block carries padding rows rather than becoming
+// a launch of its own, which would be another round). launch(ft, args, grid)
+// launches the kernel instance with ft 32-frame tiles per block.
 template <typename Launch>
 void launch_in_rounds(const srp_geometry_s* g, int F, const NyqArgs& a, int per_cu,
                       Launch&& launch) {
@@ -801,9 +802,10 @@ void launch_in_rounds(const srp_geometry_s* g, int F, const NyqArgs& a, int per_
   const int64_t n_fb = (F + 255) / 256;
   const int64_t full_cb = (n_cb * n_fb) / round * round / n_fb;
   const int64_t rest_cb = n_cb - full_cb;
+  const int ft_main = (F + 31) / 32 < 8 ? (F + 31) / 32 : 8;  // tiles of the first launch's blocks
   auto rest_fb = [&](int ft) { return (F + 32 * ft - 1) / (32 * ft); };
   int ft_rest = 0;
-  for (int ft = 4; ft <= 7 && ft_rest == 0; ++ft)
+  for (int ft = 1; ft < ft_main && ft_rest == 0; ++ft)
     if (rest_cb * rest_fb(ft) <= round) ft_rest = ft;
   const bool split = full_cb > 0 && rest_cb > 0 && ft_rest > 0;
   const unsigned gx = static_cast<unsigned>(split ? full_cb : n_cb);
@@ -815,6 +817,9 @@ void launch_in_rounds(const srp_geometry_s* g, int F, const NyqArgs& a, int per_
   b.j_base = full_cb * JB;
   const dim3 grid(static_cast<unsigned>(rest_cb), static_cast<unsigned>(rest_fb(ft_rest)));
   switch (ft_rest) {
+    case 1: launch(std::integral_constant<int, 1>(), b, grid); break;
+    case 2: launch(std::integral_constant<int, 2>(), b, grid); break;
+    case 3: launch(std::integral_constant<int, 3>(), b, grid); break;
     case 4: launch(std::integral_constant<int, 4>(), b, grid); break;
     case 5: launch(std::integral_constant<int, 5>(), b, grid); break;
     case 6: launch(std::integral_constant<int, 6>(), b, grid); break;

@@ -394,7 +394,7 @@ def wide_grid():
     # 256 candidates x 256 frames, which on a 256-CU device fill two whole
     # rounds (one workgroup per CU in FP32, two in BF16/FP16) and leave 44
     # candidate blocks, so the map call runs as two launches split at candidate
-    # 65,536 (the rest with 128-frame blocks, the last of them 44 frames)
+    # 65,536 (the rest with 64-frame blocks, the last of them 44 frames)
     return WL.make_custom(M=8, J_shape=(80, 40, 24), L=256, F=300, seed=12)
 
 
