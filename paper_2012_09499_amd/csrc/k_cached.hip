@@ -16,11 +16,12 @@
 // come from LDS here, and this square-ish wave tile reads 6 operand chunks per
 // 8 matrix-core instructions, against 9 for 32 candidates x 256 frames);
 // samples staged in 64-column tiles through LDS with a conflict-free swizzle;
-// the weights of the workgroup's 256 candidates are staged the same way (rows of
-// W are 16-byte chunks apart in the operand layout, so direct loads would
-// fetch each cache line several times); copies run one tile ahead. The frame blocks of a
-// candidate tile are placed on the same XCD at the same time (workgroup b
-// runs on XCD b mod 8), so W is read from HBM about once per launch.
+// the weights of the workgroup's 256 candidates are staged the same way (rows
+// of W are 16-byte chunks apart in the operand layout, so direct loads would
+// fetch each cache line several times); copies run one tile ahead. The frame
+// blocks of a candidate tile are placed on the same XCD at the same time
+// (workgroup b runs on XCD b mod 8), so W is read from HBM about once per
+// launch.
 #include <type_traits>
 
 #include "srp_device.h"
