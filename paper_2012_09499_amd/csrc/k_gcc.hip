@@ -26,10 +26,18 @@ template <int FT, typename OutT, int KS>
 __global__ __launch_bounds__(64 * KS) void gcc_samples_kernel(
     const float2* __restrict__ psi, const float* __restrict__ binw,
     const float2* __restrict__ table, int nw, int h_max, const LagRun* __restrict__ tiles,
-    const PairDesc* __restrict__ pairs, int F, int P, int K, int S, OutT* __restrict__ xi) {
+    int n_tiles, const PairDesc* __restrict__ pairs, int F, int P, int K, int S,
+    OutT* __restrict__ xi) {
   constexpr int U = 4;  // bins per group
   __shared__ floatx16 part[(KS > 1 ? KS - 1 : 1) * FT * 64];
-  const LagRun tl = tiles[blockIdx.x];
+  // Workgroup b runs on XCD b mod 8 (the grid's x extent is a multiple of 8):
+  // each XCD takes a contiguous range of lag tiles, so the tiles of one pair
+  // (which read the same spectra) share that XCD's L2 instead of each
+  // fetching the pair's spectra from HBM.
+  const int per_xcd = gridDim.x / 8;
+  const int ti = static_cast<int>(blockIdx.x % 8) * per_xcd + static_cast<int>(blockIdx.x / 8);
+  if (ti >= n_tiles) return;  // the whole workgroup (padding of the grid)
+  const LagRun tl = tiles[ti];
   const PairDesc pd = pairs[tl.p];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -143,9 +151,10 @@ __global__ __launch_bounds__(64 * KS) void gcc_samples_kernel(
 template <int FT, int KS, typename OutT>
 void launch_gcc(const srp_geometry_s* g, const float2* psi, int F, OutT* xi, hipStream_t s) {
   const int n_tiles = static_cast<int>(g->gcc_tiles.size());
-  const dim3 grid(n_tiles, (F + 32 * FT - 1) / (32 * FT));
+  const int gx = (n_tiles + 7) / 8 * 8;  // a multiple of the 8 XCDs (see the kernel)
+  const dim3 grid(gx, (F + 32 * FT - 1) / (32 * FT));
   hipLaunchKernelGGL((gcc_samples_kernel<FT, OutT, KS>), grid, dim3(64 * KS), 0, s, psi,
-                     g->d_binw, g->d_gcc_table, g->gcc_nw, g->info.h_max, g->d_gcc_tiles,
+                     g->d_binw, g->d_gcc_table, g->gcc_nw, g->info.h_max, g->d_gcc_tiles, n_tiles,
                      g->d_pairs, F, g->info.P, g->info.K, static_cast<int>(g->info.S), xi);
 }
 
