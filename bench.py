@@ -224,6 +224,69 @@ def paper_standin(n_sources: int = 48, frames: int = 16, seed: int = 2021):
     return res
 
 
+def next_rows_leg(srp, torch, wl, g, frames, pipe, steps):
+    """The band-limited map (f_max = fs/4: T = 2/fs, half the lags) and the
+    refined peak search from the FP32 coarse peaks, on the timed workload."""
+    dev = frames.device
+    res = {}
+    g2 = srp.Geometry(wl.mic_xyz, wl.candidates(), fs=wl.fs, L=wl.L, c=wl.c, n_aux=wl.n_aux,
+                      f_max=wl.fs / 4.0)
+    p2 = srp.SrpPipeline(g2, wl.F, device=dev, keep_map=False)
+    band = {"f_max_hz": wl.fs / 4.0, "K": g2.K, "samples_per_frame_NP": g2.W_total}
+    for dt in ("fp32", "bf16"):
+        def step(ev=None):
+            psi = srp.cross_spectra(g2, frames, out=p2.psi, workspace=p2.workspace)
+            xi = srp.gcc_samples(g2, psi, out=p2.samples_buffer(dt), dtype=dt)
+            if ev is not None:
+                ev[0].record(torch.cuda.current_stream())
+            srp.map_nyquist(g2, xi, dtype=dt, want_map=False, peaks_out=p2.peaks)
+            if ev is not None:
+                ev[1].record(torch.cuda.current_stream())
+        step()
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(steps)]
+        t0 = time.perf_counter()
+        for k in range(steps):
+            step(evs[k])
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        t_map = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+        tf = 2.0 * g2.W_total * wl.J * wl.F / (t_map * 1e-3) / 1e12
+        peak = PEAK_FP32_TFLOPS if dt == "fp32" else PEAK_BF16_TFLOPS
+        band[dt] = {"ms_per_step": ms, "map_kernel_ms": t_map,
+                    "value": wl.F * wl.J * wl.P / (ms * 1e-3), "unit": "cand-pair evals/s",
+                    "achieved_tflops": tf, "frac": tf / peak}
+    res["band_limited"] = band
+    del p2, g2
+
+    # refined search: two levels of a 3 x 3 x 3 lattice (spacing h/3, then h/9)
+    # around each frame's coarse FP32 peak, from the same samples
+    from paper_2012_09499_amd.refine import refine_peaks
+    psi = srp.cross_spectra(g, frames, out=pipe.psi, workspace=pipe.workspace)
+    xi = srp.gcc_samples(g, psi, out=pipe.samples_buffer("fp32"))
+    srp.map_nyquist(g, xi, want_map=False, peaks_out=pipe.peaks)
+    idx, _ = srp.decode_peaks(pipe.peaks)
+    start = wl.candidates()[idx]
+    h = wl.grid.h
+    refine_peaks(g, xi, start, spacing=h, levels=2)
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        pts, _ = refine_peaks(g, xi, start, spacing=h, levels=2)
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    npts = wl.F * 27 * 2
+
+    def dist(q):
+        return np.min(np.linalg.norm(q[:, None, :] - wl.sources[None, :, :], axis=-1), axis=1)
+    res["refined_search"] = {
+        "levels": 2, "lattice": "3x3x3", "points_per_frame": 54, "ms_per_call": ms,
+        "points_per_s": npts / (ms * 1e-3), "cand_pair_evals_per_s": npts * wl.P / (ms * 1e-3),
+        "median_dist_to_source_coarse_m": float(np.median(dist(start))),
+        "median_dist_to_source_refined_m": float(np.median(dist(pts)))}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -233,6 +296,8 @@ def main():
     ap.add_argument("--conv-steps", type=int, default=3)
     ap.add_argument("--no-conventional", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-next-rows", action="store_true",
+                    help="skip the band-limited map and the refined-search leg")
     ap.add_argument("--cpu-candidates", type=int, default=120000,
                     help="candidates of the oracle's timed sample (about 10 s on 16 threads)")
     ap.add_argument("--serving-seconds", type=float, default=10.0,
@@ -411,6 +476,17 @@ def main():
         del W
     else:
         out["nyquist_bf16_cached"] = {"skipped": f"W needs {w_bytes / 1e9:.0f} GB"}
+
+    if not args.no_next_rows:
+        nr = next_rows_leg(srp, torch, wl, g, frames, pipe, args.steps)
+        out["next_rows"] = nr
+        b = nr["band_limited"]
+        print(f"[bench] band-limited (f_max {b['f_max_hz']:.0f} Hz): fp32 map "
+              f"{b['fp32']['map_kernel_ms']:.2f} ms, bf16 map {b['bf16']['map_kernel_ms']:.2f} ms; "
+              f"refined search {nr['refined_search']['ms_per_call']:.2f} ms per call, median "
+              f"distance to a source {nr['refined_search']['median_dist_to_source_coarse_m']:.3f}"
+              f" -> {nr['refined_search']['median_dist_to_source_refined_m']:.3f} m",
+              file=sys.stderr, flush=True)
 
     if not args.no_conventional:
         def conv_step():
