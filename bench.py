@@ -296,8 +296,11 @@ def main():
     ap.add_argument("--conv-steps", type=int, default=3)
     ap.add_argument("--no-conventional", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-next-rows", action="store_true",
-                    help="skip the band-limited map and the refined-search leg")
+    ap.add_argument("--next-rows", action="store_true",
+                    help="also measure the band-limited map (f_max = fs/4) and the refined "
+                         "peak search (kept out of the default run: the band-limited map "
+                         "launches the same kernel instances as the timed one, which would "
+                         "mix two workloads in a kernel trace of the default command)")
     ap.add_argument("--cpu-candidates", type=int, default=120000,
                     help="candidates of the oracle's timed sample (about 10 s on 16 threads)")
     ap.add_argument("--serving-seconds", type=float, default=10.0,
@@ -477,7 +480,7 @@ def main():
     else:
         out["nyquist_bf16_cached"] = {"skipped": f"W needs {w_bytes / 1e9:.0f} GB"}
 
-    if not args.no_next_rows:
+    if args.next_rows:
         nr = next_rows_leg(srp, torch, wl, g, frames, pipe, args.steps)
         out["next_rows"] = nr
         b = nr["band_limited"]
