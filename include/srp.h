@@ -113,7 +113,9 @@ srp_status srp_pair_layout(const double* mic_xyz, int32_t M, double c, double f_
  * f_max, n_aux < 0, 2 h_p + 1 > L for some pair, a far-field direction whose
  * norm differs from 1 by more than 1e-9, a NULL pointer. Copies the tables to
  * the device on `stream` and waits for the copies before returning, so the
- * host arrays may be freed at once. */
+ * host arrays may be freed at once. The handle belongs to the device current
+ * at this call; its compute-unit count and the occupancy of the interpolation
+ * kernels are read here to size their launches. */
 srp_status srp_geometry(const double* mic_xyz, int32_t M, const double* cand_xyz, int64_t J,
                         int32_t field, double c, double fs, int32_t L, double f_max,
                         int32_t n_aux, int32_t window, void* stream, srp_geometry_t** out);
