@@ -156,7 +156,8 @@ srp_status srp_gcc_samples(const srp_geometry_t* g, const float* psi, int32_t F,
  *   psi    device, F x P x K complex64
  *   map    device, F x J float32, written; may be NULL if peaks is not
  *   peaks  device, F srp_peak, written; may be NULL if map is not
- * dtype: SRP_FP32, SRP_BF16, SRP_FP16 or SRP_FP64 (see srp_dtype). */
+ * dtype: SRP_FP32 (float32 matrix cores) or SRP_FP64 (see srp_dtype); any
+ * other dtype returns SRP_ERR_UNSUPPORTED before anything is enqueued. */
 srp_status srp_map_conventional(const srp_geometry_t* g, const float* psi, int32_t F,
                                 int32_t dtype, float* map, srp_peak* peaks, void* stream);
 
@@ -242,6 +243,9 @@ srp_status srp_map_nyquist_batched_workspace(int32_t n_items, size_t* bytes);
  *   items      host, n_items entries (read before the call returns)
  *   xi         device sample arena holding every item's samples, stored as
  *              float (SRP_FP32), bfloat16 (SRP_BF16) or half (SRP_FP16)
+ *   xi_elems   number of elements of the arena; an item whose samples
+ *              [xi_offset, xi_offset + F S) do not lie inside it is rejected
+ *              with SRP_ERR_INVALID_ARG before anything is enqueued
  *   dtype      SRP_FP32: float32 on the vector units (with one to eight
  *              frames per array the weights are formed once per candidate and
  *              lag and used by those frames only), the accuracy of
@@ -259,8 +263,8 @@ srp_status srp_map_nyquist_batched_workspace(int32_t n_items, size_t* bytes);
  *              another batch on another stream before then)
  * All items must live on one device. */
 srp_status srp_map_nyquist_batched(const srp_batch_item* items, int32_t n_items, const void* xi,
-                                   int32_t dtype, void* workspace, size_t workspace_bytes,
-                                   void* stream);
+                                   int64_t xi_elems, int32_t dtype, void* workspace,
+                                   size_t workspace_bytes, void* stream);
 
 /* Per-frame argmax of a map (Section 2.2), lowest index on ties.
  *   map    device, F x J float32;  peaks device, F srp_peak, written.

@@ -24,6 +24,14 @@ def sample_torch_dtype(dtype: str):
     import torch
     return {"fp32": torch.float32, "fp64": torch.float32, "bf16": torch.bfloat16,
             "fp16": torch.float16}[dtype]
+# dtypes srp_map_conventional has a kernel for (others return SRP_ERR_UNSUPPORTED)
+CONVENTIONAL_DTYPES = ("fp32", "fp64")
+
+
+def conventional_supports(dtype: str) -> bool:
+    return dtype in CONVENTIONAL_DTYPES
+
+
 FIELDS = {"near": 0, "far": 1}
 WINDOWS = {"hann": 0, "sqrt_hann": 1, "rect": 2}
 PHAT = 0
@@ -87,7 +95,7 @@ def lib() -> C.CDLL:
     L.srp_map_nyquist.argtypes = [vp, vp, i32, i32, vp, vp, vp]
     L.srp_argmax.argtypes = [vp, i32, i64, vp, vp]
     L.srp_map_nyquist_batched_workspace.argtypes = [i32, C.POINTER(C.c_size_t)]
-    L.srp_map_nyquist_batched.argtypes = [vp, i32, vp, i32, vp, C.c_size_t, vp]
+    L.srp_map_nyquist_batched.argtypes = [vp, i32, vp, i64, i32, vp, C.c_size_t, vp]
     L.srp_nyquist_weights_bytes.argtypes = [vp, i32, C.POINTER(C.c_size_t)]
     L.srp_nyquist_weights.argtypes = [vp, i32, vp, C.c_size_t, vp]
     L.srp_map_nyquist_cached.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp]
@@ -385,7 +393,8 @@ def map_nyquist_batched(items, xi_arena, workspace, stream=None, dtype: str = "f
         arr[i].F = int(F)
         arr[i].map = m.data_ptr() if m is not None else None
         arr[i].peaks = pk.data_ptr() if pk is not None else None
-    _check(lib().srp_map_nyquist_batched(arr, n, xi_arena.data_ptr(), DTYPES[dtype],
+    _check(lib().srp_map_nyquist_batched(arr, n, xi_arena.data_ptr(), xi_arena.numel(),
+                                         DTYPES[dtype],
                                          workspace.data_ptr(),
                                          workspace.numel() * workspace.element_size(),
                                          _stream_handle(stream)))

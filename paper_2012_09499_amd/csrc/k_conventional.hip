@@ -368,6 +368,8 @@ __global__ __launch_bounds__(256) void conventional_f64_kernel(ConvArgs a) {
 
 }  // namespace
 
+bool conventional_supports(int dtype) { return dtype == SRP_FP32 || dtype == SRP_FP64; }
+
 hipError_t launch_conventional(const srp_geometry_s* g, const float2* psi, int F, int dtype,
                                float* map, unsigned long long* keys, hipStream_t s) {
   ConvArgs a;

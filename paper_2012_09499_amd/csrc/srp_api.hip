@@ -484,6 +484,10 @@ srp_status srp_map_conventional(const srp_geometry_t* g, const float* psi, int32
                                 int32_t dtype, float* map, srp_peak* peaks, void* stream) {
   srp_status st = check_map_args(g, psi, F, dtype, map, peaks);
   if (st != SRP_OK) return st;
+  // every dtype without a kernel is refused here, before the peaks are
+  // initialised, so an unsupported call writes nothing
+  if (!conventional_supports(dtype))
+    return fail(SRP_ERR_UNSUPPORTED, "srp_map_conventional: dtype not supported");
   DeviceGuard dg(g->device);
   if (!dg.ok) return fail(SRP_ERR_DEVICE, "cannot select the geometry's device");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -493,7 +497,6 @@ srp_status srp_map_conventional(const srp_geometry_t* g, const float* psi, int32
     e = launch_conventional(g, reinterpret_cast<const float2*>(psi), F, dtype, map,
                             reinterpret_cast<unsigned long long*>(peaks), s);
   if (e == hipSuccess && peaks) e = launch_peaks_finalize(peaks, F, s);
-  if (e == hipErrorNotSupported) return fail(SRP_ERR_UNSUPPORTED, "dtype not supported here");
   if (e != hipSuccess) return device_fail(e, "map_conventional");
   return SRP_OK;
 }
@@ -505,11 +508,12 @@ srp_status srp_map_nyquist_batched_workspace(int32_t n_items, size_t* bytes) {
 }
 
 srp_status srp_map_nyquist_batched(const srp_batch_item* items, int32_t n_items, const void* xi,
-                                   int32_t dtype, void* workspace, size_t workspace_bytes,
-                                   void* stream) {
+                                   int64_t xi_elems, int32_t dtype, void* workspace,
+                                   size_t workspace_bytes, void* stream) {
   if (items == nullptr || xi == nullptr || workspace == nullptr)
     return fail(SRP_ERR_INVALID_ARG, "srp_map_nyquist_batched: NULL argument");
   if (n_items < 1) return fail(SRP_ERR_INVALID_ARG, "n_items must be >= 1");
+  if (xi_elems < 1) return fail(SRP_ERR_INVALID_ARG, "xi_elems must be >= 1");
   if (dtype != SRP_FP32 && dtype != SRP_BF16 && dtype != SRP_FP16)
     return fail(SRP_ERR_UNSUPPORTED, "batched samples must be FP32, BF16 or FP16");
   const bool mx = dtype != SRP_FP32;
@@ -536,6 +540,10 @@ srp_status srp_map_nyquist_batched(const srp_batch_item* items, int32_t n_items,
         if (it.map == nullptr && it.peaks == nullptr)
           return fail(SRP_ERR_INVALID_ARG, "item map and peaks are both NULL");
         if (it.xi_offset < 0) return fail(SRP_ERR_INVALID_ARG, "negative xi_offset");
+        // the item's F x S samples must lie inside the arena
+        if (it.xi_offset > xi_elems ||
+            (int64_t)it.F * it.g->info.S > xi_elems - it.xi_offset)
+          return fail(SRP_ERR_INVALID_ARG, "item samples extend past the end of xi");
         if (mx && it.xi_offset % kSampleAlign != 0)
           return fail(SRP_ERR_INVALID_ARG, "BF16/FP16 xi_offset must be a multiple of 8");
         if (device >= 0 && it.g->device != device)

@@ -117,6 +117,7 @@ hipError_t launch_gcc_samples(const srp_geometry_s* g, const float2* psi, int F,
 int nyquist_workgroups_per_cu(int dtype);  // occupancy of the interpolation kernels
 hipError_t launch_nyquist(const srp_geometry_s* g, const void* xi, int F, int dtype, float* map,
                           unsigned long long* keys, hipStream_t s);
+bool conventional_supports(int dtype);  // dtypes srp_map_conventional has a kernel for
 hipError_t launch_conventional(const srp_geometry_s* g, const float2* psi, int F, int dtype,
                                float* map, unsigned long long* keys, hipStream_t s);
 // Items [0, n_vec) go to the vector-unit kernel, [n_vec, n_vec + n_mx) to the

@@ -111,3 +111,16 @@ def test_pair_layout_rejects_invalid():
         S.pair_layout(np.zeros((3, 3)), 343.0, 8000.0, -1)
     with pytest.raises(S.SrpError):
         S.pair_layout(np.full((3, 3), np.nan), 343.0, 8000.0, 0)
+
+
+def test_batched_rejects_empty_arena_without_device():
+    lib = S.lib()
+    items = (S.BatchItem * 1)()
+    buf = C.create_string_buffer(256)
+    # a NULL item geometry and an empty arena are refused before any device work
+    assert lib.srp_map_nyquist_batched(items, 1, buf, 0, 0, buf, 256, None) == \
+        S.SRP_ERR_INVALID_ARG
+    assert "xi_elems" in lib.srp_last_error().decode()
+    assert lib.srp_map_nyquist_batched(items, 1, buf, 64, 0, buf, 256, None) == \
+        S.SRP_ERR_INVALID_ARG
+    assert "geometry" in lib.srp_last_error().decode()

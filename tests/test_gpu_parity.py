@@ -430,3 +430,25 @@ def test_nyquist_launch_split_boundary(wide_grid, dtype):
         rows = np.arange(wl.F)
         peak = ref[rows, np.argmax(ref, axis=1)]
         assert np.all(peak - ref[rows, idx] <= 2.0 * tol * np.abs(peak))
+
+
+def test_conventional_unsupported_dtype_writes_nothing(cases):
+    """A dtype without a conventional kernel is refused before anything is enqueued:
+    the caller's map and peaks keep their contents."""
+    wl = cases["m4_L256_F3"]
+    g = _geom(wl)
+    psi = srp.cross_spectra(g, _frames(wl))
+    pk = torch.full((wl.F, 2), -12345, dtype=torch.int64, device="cuda")
+    m = torch.full((wl.F, g.J), 7.0, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    for dt in [d for d in ("bf16", "fp16") if not srp.conventional_supports(d)]:
+        with pytest.raises(srp.SrpError) as e:
+            srp.map_conventional(g, psi, dtype=dt, map_out=m, peaks_out=pk)
+        assert e.value.status == srp.SRP_ERR_UNSUPPORTED
+    # an unknown dtype code is an invalid argument, also before anything runs
+    lib = srp.lib()
+    st = lib.srp_map_conventional(g.handle, psi.data_ptr(), wl.F, 9, m.data_ptr(),
+                                  pk.data_ptr(), None)
+    assert st == srp.SRP_ERR_INVALID_ARG
+    torch.cuda.synchronize()
+    assert bool((pk == -12345).all()) and bool((m == 7.0).all())

@@ -126,6 +126,13 @@ def test_batched_argument_checks():
         srp.map_nyquist_batched([(g, 0, 1, None, pk[:1])], x16[1:], ws, dtype="bf16")
     with pytest.raises(TypeError):
         srp.map_nyquist_batched([(g, 0, 1, None, pk[:1])], x32, ws, dtype="bf16")
+    # an item's F x S samples must lie inside the arena
+    with pytest.raises(srp.SrpError, match="past the end"):      # arena of one frame
+        srp.map_nyquist_batched([(g, 0, 2, None, pk[:2])], x32[:g.S], ws)
+    with pytest.raises(srp.SrpError, match="past the end"):      # offset near the end
+        srp.map_nyquist_batched([(g, 16 * g.S + 8, 1, None, pk[:1])], x16, ws, dtype="bf16")
+    with pytest.raises(srp.SrpError, match="past the end"):      # offset past the end
+        srp.map_nyquist_batched([(g, 18 * g.S, 1, None, pk[:1])], x32, ws)
     # the checks happen before anything runs: a valid call still works afterwards
     srp.map_nyquist_batched([(g, 0, 16, None, pk[:16])], x16, ws, dtype="bf16")
     torch.cuda.synchronize()
