@@ -11,8 +11,8 @@
   arrays the kernel read (float32 accumulation: 1e-5 relative), and the
   oracle's float64 Nyquist map within the BF16/FP16 tolerance 1e-2, with the
   argmax checked as for every other map.
-* The room-scale workload (16 mics, 576,000 candidates, 500 frames) on
-  sampled candidates, and argument errors.
+* Argument errors. (The room-scale workload, 16 mics / 576,000 candidates /
+  500 frames, is checked over its whole map in test_gpu_fullsize.py.)
 """
 import numpy as np
 import pytest
@@ -109,47 +109,37 @@ def test_weights_are_rounded_float64_sinc(cases, name, dtype):
 def test_cached_map_is_the_product_and_matches_oracle(cases, name, dtype):
     wl = cases[name]
     g = _geom(wl)
+    tdt = srp.sample_torch_dtype(dtype)
+    xi_ref = R.oracle_xi(wl, R.oracle_psi(wl))
+    # the product kernel alone: the oracle's weights and samples, each rounded
+    # once to the storage type, feed the kernel; their product in float64 is the
+    # expected map (float32 accumulation: 1e-5 relative)
+    cols = srp.nyquist_weights_bytes(g, dtype) // (2 * g.J)
+    Wr = _round(_ref_weights(wl, wl.candidates(), cols), dtype)
+    W_in = torch.from_numpy(Wr).to(tdt).cuda()
+    xi_in, xr = R.device_samples(g, xi_ref, tdt)
+    m, pk = srp.map_nyquist_cached(g, W_in, xi_in, dtype=dtype)
+    torch.cuda.synchronize()
+    got = m.cpu().numpy().astype(np.float64)
+    full = np.zeros((wl.F, g.S))
+    full[:, R.sample_columns(g)] = xr
+    prod = 2.0 * full @ Wr[:, :g.S].T
+    assert O.rel_error(got, prod).max() <= 1e-5
+    np.testing.assert_array_equal(srp.decode_peaks(pk)[0], np.argmax(got, axis=1))
+    del W_in
+    # the whole cached path (library weights, samples from the frames) against
+    # the float64 oracle map of the frames, within the BF16/FP16 tolerance
     W = srp.nyquist_weights(g, dtype)
     fr = torch.from_numpy(wl.frames).cuda()
     xi = srp.gcc_samples(g, srp.cross_spectra(g, fr), dtype=dtype)
     m, pk = srp.map_nyquist_cached(g, W, xi, dtype=dtype)
     torch.cuda.synchronize()
     got = m.cpu().numpy().astype(np.float64)
-    # the product of exactly the arrays the kernel read, in float64
-    Wd = W.to(torch.float64).cpu().numpy()[:, :g.S]
-    xd = xi.to(torch.float64).cpu().numpy()
-    prod = 2.0 * xd @ Wd.T
-    assert O.rel_error(got, prod).max() <= 1e-5
-    # and the float64 oracle map, within the BF16/FP16 tolerance
-    ref = R.oracle_nyquist(wl, R.oracle_xi(wl, R.oracle_psi(wl)), wl.candidates())
+    ref = R.oracle_nyquist(wl, xi_ref, wl.candidates())
     assert O.rel_error(got, ref).max() <= TOL
     idx = srp.decode_peaks(pk)[0]
     np.testing.assert_array_equal(idx, np.argmax(got, axis=1))
-    R.check_argmax(idx, ref, TOL)
-    g.close()
-
-
-def test_cached_room_scale_full_size():
-    """16 mics, 576,000 candidates, 500 frames (the bench workload), BF16."""
-    wl = WL.make(2)
-    g = _geom(wl)
-    W = srp.nyquist_weights(g, "bf16")
-    pipe = srp.SrpPipeline(g, wl.F, keep_map=True)
-    m, pk = pipe.nyquist(torch.from_numpy(wl.frames).cuda(), dtype="bf16", weights=W)
-    torch.cuda.synchronize()
-    assert bool(torch.isfinite(m).all())
-    idx = srp.decode_peaks(pk)[0]
-    np.testing.assert_array_equal(idx, torch.argmax(m, dim=1).cpu().numpy())
-    rng = np.random.default_rng(0)
-    sel = np.unique(np.concatenate([rng.choice(wl.J, 3000, replace=False), idx]))
-    got = m[:, torch.from_numpy(sel).cuda()].cpu().numpy().astype(np.float64)
-    ref = R.oracle_nyquist(wl, R.oracle_xi(wl, R.oracle_psi(wl)), wl.candidates_at(sel))
-    assert O.rel_error(got, ref).max() <= TOL
-    # the on-the-fly BF16 kernel agrees on the peaks up to near-ties
-    m2, pk2 = srp.SrpPipeline(g, wl.F).nyquist(torch.from_numpy(wl.frames).cuda(), dtype="bf16")
-    torch.cuda.synchronize()
-    assert (srp.decode_peaks(pk2)[0] == idx).mean() >= 0.99
-    del W, m, pipe
+    R.check_argmax(idx, ref, TOL, label=f"cached/{name}/{dtype}")
     g.close()
 
 

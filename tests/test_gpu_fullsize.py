@@ -1,15 +1,31 @@
-"""GPU parity at full workload sizes, on sampled outputs.
+"""GPU parity at full workload sizes.
 
-The room-scale workload runs exactly as bench.py times it (16 mics, 576,000
-candidates, 500 frames). The two largest geometries (32 mics / 4,000,000
-candidates / L = 2048, and 64 mics / 9,000,000 candidates / 48 kHz / L = 4096)
-run at full geometry with fewer frames. The oracle evaluates a sample of
-candidates: seeded random ones plus the 3x3x3 neighbourhoods of every true
-source and of the GPU's per-frame argmax. Checks on the full GPU output: every
-map value is finite and the peaks are the map's argmax. Checks on the sample:
-relative L2 error per frame within the dtype's tolerance, and the GPU argmax
-is a maximum of the oracle map over the sample up to that tolerance.
+Room scale (16 mics, 576,000 candidates, 500 frames; the configuration bench.py
+times): the float64 oracle evaluates the WHOLE map, every candidate and every
+frame, once per module (candidate chunks in threads). Each GPU map (FP32, BF16,
+FP16 on the fly, BF16 from cached weights) is checked over the whole map:
+relative L2 error per frame within the dtype's tolerance, peaks equal to the
+map's argmax, and the argmax identical to the oracle's in at least 99 % of the
+frames with every other frame a near-tie (Section 2.2: the estimate is the
+argmax).
+
+32 mics / 4,000,000 candidates / L = 2048, all 200 frames: the oracle map of a
+seeded subset (20,000 random candidates plus the 3x3x3 neighbourhoods of every
+true source and of the GPU's per-frame argmax) bounds the error, and the
+argmax is compared over all 200 frames with the oracle's whole-map peaks
+stored in tests/golden/ (written by tests/golden/make_oracle_peaks.py, which
+calls only the oracle and the input generator).
+
+64 mics / 9,000,000 candidates / 48 kHz / L = 4096 (its whole oracle map would
+take hours): 3 frames, the subset protocol, and the GPU pick must be a maximum
+of the oracle map over the subset up to the tolerance.
+
+The conventional map at room scale is checked on a candidate sample (its whole
+oracle map, J P K complex products per frame, is out of reach of a CPU test).
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -23,6 +39,7 @@ torch = pytest.importorskip("torch")
 import paper_2012_09499_amd as srp  # noqa: E402
 
 TOL = {"fp32": 1e-5, "bf16": 1e-2, "fp16": 1e-2}
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def _neighbourhood(grid, idx):
@@ -47,43 +64,57 @@ def _sample(wl, gpu_idx, n_random, seed=0):
     return np.unique(np.concatenate(parts))
 
 
-def _check(wl, g, m, pk, dtype, xi_ref, n_random):
-    tol = TOL[dtype]
-    assert bool(torch.isfinite(m).all())
-    idx = srp.decode_peaks(pk)[0]
-    np.testing.assert_array_equal(idx, torch.argmax(m, dim=1).cpu().numpy())
-    sel = _sample(wl, idx, n_random)
-    got = m[:, torch.from_numpy(sel).to(m.device)].cpu().numpy().astype(np.float64)
-    ref = R.oracle_nyquist(wl, xi_ref, wl.candidates_at(sel))
-    err = O.rel_error(got, ref)
-    assert err.max() <= tol, (dtype, err.max())
-    # the GPU pick is a maximum of the oracle map over the sample, up to the tolerance
-    pos = np.searchsorted(sel, idx)
-    scale = np.linalg.norm(ref, axis=1) * np.sqrt(wl.J / sel.size)
-    gap = ref.max(axis=1) - ref[np.arange(ref.shape[0]), pos]
-    assert np.all(gap <= 2 * tol * scale), (gap.max(), scale.min())
-    return err.max()
+def _geom(wl):
+    return srp.Geometry(wl.mic_xyz, wl.candidates(), fs=wl.fs, L=wl.L, c=wl.c, n_aux=wl.n_aux)
 
+
+# ------------------------------------------------------------------ room scale
 
 @pytest.fixture(scope="module")
 def room():
     wl = WL.make(2)
-    g = srp.Geometry(wl.mic_xyz, wl.candidates(), fs=wl.fs, L=wl.L, c=wl.c, n_aux=wl.n_aux)
+    g = _geom(wl)
     xi_ref = R.oracle_xi(wl, R.oracle_psi(wl))
-    return wl, g, xi_ref
+    print(f"[fullsize] room-scale oracle map: {wl.J} candidates x {wl.F} frames", flush=True)
+    ref = R.oracle_nyquist_parallel(wl, xi_ref)
+    return wl, g, xi_ref, ref
 
 
+def _check_whole_map(label, m, pk, ref, tol):
+    assert bool(torch.isfinite(m).all())
+    got = m.cpu().numpy().astype(np.float64)
+    idx = srp.decode_peaks(pk)[0]
+    np.testing.assert_array_equal(idx, np.argmax(got, axis=1))
+    err = O.rel_error(got, ref)
+    assert err.max() <= tol, (label, err.max())
+    frac = R.check_argmax(idx, ref, tol, label=label)
+    print(f"[fullsize] {label}: max rel err {err.max():.2e}, argmax identical in "
+          f"{100 * frac:.1f} % of {ref.shape[0]} frames", flush=True)
+
+
+@pytest.mark.timeout(900)
 @pytest.mark.parametrize("dtype", ["fp32", "bf16", "fp16"])
-def test_room_scale_full_size_nyquist(room, dtype):
-    wl, g, xi_ref = room
+def test_room_scale_whole_map_nyquist(room, dtype):
+    wl, g, _, ref = room
     pipe = srp.SrpPipeline(g, wl.F, keep_map=True)
     m, pk = pipe.nyquist(torch.from_numpy(wl.frames).cuda(), dtype=dtype)
     torch.cuda.synchronize()
-    _check(wl, g, m, pk, dtype, xi_ref, n_random=3000)
+    _check_whole_map(f"room-whole-map/{dtype}", m, pk, ref, TOL[dtype])
+
+
+@pytest.mark.timeout(900)
+def test_room_scale_whole_map_cached_bf16(room):
+    wl, g, _, ref = room
+    W = srp.nyquist_weights(g, "bf16")
+    pipe = srp.SrpPipeline(g, wl.F, keep_map=True)
+    m, pk = pipe.nyquist(torch.from_numpy(wl.frames).cuda(), dtype="bf16", weights=W)
+    torch.cuda.synchronize()
+    del W
+    _check_whole_map("room-whole-map/cached-bf16", m, pk, ref, TOL["bf16"])
 
 
 def test_room_scale_full_size_conventional(room):
-    wl, g, _ = room
+    wl, g, _, _ = room
     pipe = srp.SrpPipeline(g, wl.F, keep_map=True)
     m, pk = pipe.conventional(torch.from_numpy(wl.frames).cuda())
     torch.cuda.synchronize()
@@ -96,24 +127,89 @@ def test_room_scale_full_size_conventional(room):
     assert O.rel_error(got, ref).max() <= 1e-5
 
 
-@pytest.mark.parametrize("cfg,F,n_random", [(3, 8, 2000), (5, 2, 300)])
-@pytest.mark.parametrize("dtype", ["fp32", "bf16"])
-def test_largest_geometries_nyquist(cfg, F, n_random, dtype):
-    wl = WL.make(cfg, F=F)
-    g = srp.Geometry(wl.mic_xyz, wl.candidates(), fs=wl.fs, L=wl.L, c=wl.c, n_aux=wl.n_aux)
+# ------------------------------------------------------- the larger geometries
+
+def _subset_check(wl, m, pk, dtype, xi_ref, n_random):
+    tol = TOL[dtype]
+    assert bool(torch.isfinite(m).all())
+    idx = srp.decode_peaks(pk)[0]
+    np.testing.assert_array_equal(idx, torch.argmax(m, dim=1).cpu().numpy())
+    sel = _sample(wl, idx, n_random)
+    got = m[:, torch.from_numpy(sel).to(m.device)].cpu().numpy().astype(np.float64)
+    ref = R.oracle_nyquist_parallel(wl, xi_ref, idx=sel)
+    err = O.rel_error(got, ref)
+    assert err.max() <= tol, (dtype, err.max())
+    # the GPU pick is a maximum of the oracle map over the subset, up to the tolerance
+    pos = np.searchsorted(sel, idx)
+    scale = np.linalg.norm(ref, axis=1) * np.sqrt(wl.J / sel.size)
+    gap = ref.max(axis=1) - ref[np.arange(ref.shape[0]), pos]
+    assert np.all(gap <= 2 * tol * scale), (gap.max(), scale.min())
+    return idx, err.max()
+
+
+@pytest.fixture(scope="module")
+def precision_geometry():
+    """32 mics, 4,000,000 candidates, L = 2048, all 200 frames."""
+    wl = WL.make(3)
+    g = _geom(wl)
+    xi_ref = R.oracle_xi(wl, R.oracle_psi(wl))
+    path = os.path.join(GOLDEN, f"oracle_nyquist_peaks_{wl.name}.json")
+    with open(path) as f:
+        peaks = json.load(f)
+    assert peaks["F"] == wl.F and peaks["J"] == wl.J
+    yield wl, g, xi_ref, peaks
+    g.close()
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("dtype", ["fp32", "bf16", "fp16"])
+def test_precision_geometry_all_frames(precision_geometry, dtype):
+    wl, g, xi_ref, peaks = precision_geometry
+    tol = TOL[dtype]
     pipe = srp.SrpPipeline(g, wl.F, keep_map=True)
     m, pk = pipe.nyquist(torch.from_numpy(wl.frames).cuda(), dtype=dtype)
     torch.cuda.synchronize()
-    xi_ref = R.oracle_xi(wl, R.oracle_psi(wl))
-    _check(wl, g, m, pk, dtype, xi_ref, n_random=n_random)
+    idx, err = _subset_check(wl, m, pk, dtype, xi_ref, n_random=20000)
     del m, pipe
+    # argmax over all frames against the oracle's whole-map peaks
+    ref_idx = np.asarray(peaks["argmax"])
+    ref_max = np.asarray(peaks["max"])
+    l2 = np.asarray(peaks["l2"])
+    same = idx == ref_idx
+    R.ARGMAX_LOG.append((f"precision-whole-map/{dtype}", int(same.sum()), int(same.size)))
+    for f in np.nonzero(~same)[0]:
+        v = R.oracle_nyquist(wl, xi_ref[f:f + 1], wl.candidates_at(idx[f:f + 1]))[0, 0]
+        assert ref_max[f] - v <= 2 * tol * l2[f], (f, ref_max[f] - v, 2 * tol * l2[f])
+    assert same.mean() >= 0.99, same.mean()
+    print(f"[fullsize] precision geometry {dtype}: subset rel err {err:.2e}, argmax identical "
+          f"in {100 * same.mean():.1f} % of {wl.F} frames", flush=True)
+
+
+@pytest.fixture(scope="module")
+def largest_array():
+    """64 mics / 9,000,000 candidates / 48 kHz / L = 4096, 3 frames."""
+    wl = WL.make(5, F=3)
+    g = _geom(wl)
+    xi_ref = R.oracle_xi(wl, R.oracle_psi(wl))
+    yield wl, g, xi_ref
     g.close()
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("dtype", ["fp32", "bf16", "fp16"])
+def test_largest_array_nyquist(largest_array, dtype):
+    wl, g, xi_ref = largest_array
+    pipe = srp.SrpPipeline(g, wl.F, keep_map=True)
+    m, pk = pipe.nyquist(torch.from_numpy(wl.frames).cuda(), dtype=dtype)
+    torch.cuda.synchronize()
+    _subset_check(wl, m, pk, dtype, xi_ref, n_random=600)
+    del m, pipe
 
 
 def test_largest_geometry_conventional():
     """32 mics / 4,000,000 candidates / L = 2048 (two-level-sum variant), 8 frames."""
     wl = WL.make(3, F=8)
-    g = srp.Geometry(wl.mic_xyz, wl.candidates(), fs=wl.fs, L=wl.L, c=wl.c, n_aux=wl.n_aux)
+    g = _geom(wl)
     pipe = srp.SrpPipeline(g, wl.F, keep_map=True)
     m, pk = pipe.conventional(torch.from_numpy(wl.frames).cuda())
     torch.cuda.synchronize()

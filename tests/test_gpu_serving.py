@@ -83,7 +83,7 @@ def test_batched_alone_equals_mixed_and_single_kernel_and_oracle():
         assert O.rel_error(got, ref).max() <= 1e-5
         idx = srp.decode_peaks(mixed[i][1])[0]
         np.testing.assert_array_equal(idx, np.argmax(got, axis=1))
-        R.check_argmax(idx, ref, 1e-5)
+        R.check_argmax(idx, ref, 1e-5, label=f"serving-batched/{i}/fp32")
 
 
 @pytest.mark.parametrize("dtype", ["bf16", "fp16"])
@@ -104,7 +104,7 @@ def test_batched_lowp_alone_equals_mixed_and_oracle(dtype):
         assert err.max() <= 1e-2, (dtype, i, err.max())
         idx = srp.decode_peaks(mixed[i][1])[0]
         np.testing.assert_array_equal(idx, np.argmax(got, axis=1))
-        R.check_argmax(idx, ref, 1e-2)
+        R.check_argmax(idx, ref, 1e-2, label=f"serving-batched/{i}/{dtype}")
 
 
 def test_batched_argument_checks():
