@@ -141,6 +141,21 @@ srp_status srp_cross_spectra(const srp_geometry_t* g, const float* frames, int32
                              int32_t weighting, void* workspace, size_t workspace_bytes,
                              float* psi, void* stream);
 
+/* srp_cross_spectra without a workspace argument and without any device
+ * allocation, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc). The
+ * per-microphone unit phasors are staged in a buffer the library owns: one
+ * static device array of 64 MiB per GPU, present from the library's load
+ * until the process ends, its address looked up once per device at the first
+ * call there. Same arguments, result and errors as srp_cross_spectra, except:
+ *   F * M * K * 8 bytes must not exceed 64 MiB, else SRP_ERR_INVALID_ARG with
+ *   nothing enqueued (e.g. F <= 1022 for 16 mics and K = 513).
+ * Every call on a GPU shares that GPU's buffer: calls that overlap on one GPU
+ * (several streams or threads at once) race and must be serialised by the
+ * caller. The call itself allocates nothing. */
+srp_status srp_cross_spectra_noalloc(const srp_geometry_t* g, const float* frames, int32_t F,
+                                     int32_t weighting, float* psi, void* stream);
+
 /* GCC samples at the critical lags (Section 3.2, first step; cost Eq.
  * SRPapproxcompC): xi[f][offset_p + n + h_p] = xi_p(n T) for |n| <= h_p.
  *   psi    device, F x P x K complex64 as written by srp_cross_spectra

@@ -38,7 +38,8 @@ PHAT = 0
 
 # exported symbols of include/srp.h
 EXPORTS = ("srp_pair_layout", "srp_geometry", "srp_geometry_query", "srp_geometry_destroy",
-           "srp_cross_spectra_workspace", "srp_cross_spectra", "srp_gcc_samples",
+           "srp_cross_spectra_workspace", "srp_cross_spectra", "srp_cross_spectra_noalloc",
+           "srp_gcc_samples",
            "srp_map_conventional", "srp_map_nyquist", "srp_map_nyquist_batched_workspace",
            "srp_map_nyquist_batched", "srp_nyquist_weights_bytes", "srp_nyquist_weights",
            "srp_map_nyquist_cached", "srp_map_nyquist_points", "srp_argmax", "srp_last_error",
@@ -90,6 +91,7 @@ def lib() -> C.CDLL:
     L.srp_geometry_destroy.restype = None
     L.srp_cross_spectra_workspace.argtypes = [vp, i32, C.POINTER(C.c_size_t)]
     L.srp_cross_spectra.argtypes = [vp, vp, i32, i32, vp, C.c_size_t, vp, vp]
+    L.srp_cross_spectra_noalloc.argtypes = [vp, vp, i32, i32, vp, vp]
     L.srp_gcc_samples.argtypes = [vp, vp, i32, i32, vp, vp]
     L.srp_map_conventional.argtypes = [vp, vp, i32, i32, vp, vp, vp]
     L.srp_map_nyquist.argtypes = [vp, vp, i32, i32, vp, vp, vp]
@@ -220,6 +222,24 @@ def cross_spectra(g: Geometry, frames, out=None, workspace=None, stream=None):
     _check(lib().srp_cross_spectra(g.handle, frames.data_ptr(), F, PHAT, workspace.data_ptr(),
                                    workspace.numel() * workspace.element_size(), out.data_ptr(),
                                    _stream_handle(stream)))
+    return out
+
+
+CROSS_STATIC_BYTES = 64 << 20  # the library's static phasor buffer per GPU
+
+
+def cross_spectra_noalloc(g: Geometry, frames, out, stream=None):
+    """frames [F][M][L] float32 -> psi [F][P][K] complex64 into `out`, staging the
+    per-microphone phasors in the library's static buffer (srp_cross_spectra_noalloc).
+    Nothing is allocated: the caller passes the output."""
+    import torch
+    _need_cuda(frames, "frames", torch.float32)
+    F = frames.shape[0]
+    if frames.dim() != 3 or frames.shape[1] != g.M or frames.shape[2] != g.L:
+        raise ValueError(f"frames must be [F][{g.M}][{g.L}]")
+    _need_cuda(out, "psi", torch.complex64, (F, g.P, g.K))
+    _check(lib().srp_cross_spectra_noalloc(g.handle, frames.data_ptr(), F, PHAT, out.data_ptr(),
+                                           _stream_handle(stream)))
     return out
 
 

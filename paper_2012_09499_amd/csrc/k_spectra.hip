@@ -9,6 +9,8 @@
 //
 // Step 2 (cross): psi_p(k) = ytil_m(k) conj(ytil_m'(k)) for every pair,
 // written as interleaved complex float32 [F][P][K].
+#include <mutex>
+
 #include "srp_internal.h"
 
 namespace srp {
@@ -81,6 +83,35 @@ hipError_t launch_fft_phat(const srp_geometry_s* g, const float* frames, int F, 
                      L * sizeof(float2), s, frames, g->d_window, g->d_twiddle, L, g->log2L,
                      g->info.K, ytil);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Library-owned staging of the per-microphone unit phasors for callers that
+// cannot allocate device memory (srp_cross_spectra_noalloc). One array per
+// GPU, held until the process ends. Every call on a GPU reuses it: fft_phat
+// writes every element that cross then reads, so nothing needs clearing, and
+// calls that overlap on one GPU race on it.
+static __device__ __align__(256) float2 scratch[kCrossStaticElems];
+
+namespace {
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t cross_static_scratch(int device, float2** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (g_scratch_ptr[device] == nullptr) {
+    // the caller has made `device` current: the symbol's address on that GPU
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (p == nullptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = p;
+  }
+  *out = static_cast<float2*>(g_scratch_ptr[device]);
+  return hipSuccess;
 }
 
 hipError_t launch_cross(const srp_geometry_s* g, const float2* ytil, int F, float2* psi,

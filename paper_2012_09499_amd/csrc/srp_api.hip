@@ -376,6 +376,29 @@ srp_status srp_cross_spectra(const srp_geometry_t* g, const float* frames, int32
   return SRP_OK;
 }
 
+srp_status srp_cross_spectra_noalloc(const srp_geometry_t* g, const float* frames, int32_t F,
+                                     int32_t weighting, float* psi, void* stream) {
+  if (g == nullptr || frames == nullptr || psi == nullptr)
+    return fail(SRP_ERR_INVALID_ARG, "srp_cross_spectra_noalloc: NULL argument");
+  if (F < 1) return fail(SRP_ERR_INVALID_ARG, "F must be >= 1");
+  if (weighting != SRP_PHAT) return fail(SRP_ERR_UNSUPPORTED, "only PHAT weighting");
+  const size_t need = (size_t)F * g->info.M * g->info.K;
+  if (need > kCrossStaticElems)
+    return fail(SRP_ERR_INVALID_ARG,
+                "srp_cross_spectra_noalloc: F * M * K * 8 bytes exceed the 64 MiB static buffer");
+  DeviceGuard dg(g->device);
+  if (!dg.ok) return fail(SRP_ERR_DEVICE, "cannot select the geometry's device");
+  float2* ytil = nullptr;
+  hipError_t e = cross_static_scratch(g->device, &ytil);
+  if (e != hipSuccess) return device_fail(e, "static scratch address");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  e = launch_fft_phat(g, frames, F, ytil, s);
+  if (e != hipSuccess) return device_fail(e, "fft_phat");
+  e = launch_cross(g, ytil, F, reinterpret_cast<float2*>(psi), s);
+  if (e != hipSuccess) return device_fail(e, "cross");
+  return SRP_OK;
+}
+
 srp_status srp_gcc_samples(const srp_geometry_t* g, const float* psi, int32_t F, int32_t dtype,
                            void* xi, void* stream) {
   if (g == nullptr || psi == nullptr || xi == nullptr)

@@ -112,6 +112,12 @@ hipError_t launch_fft_phat(const srp_geometry_s* g, const float* frames, int F, 
                            hipStream_t s);
 hipError_t launch_cross(const srp_geometry_s* g, const float2* ytil, int F, float2* psi,
                         hipStream_t s);
+// Per-microphone phasor staging owned by the library (srp_cross_spectra_noalloc):
+// kCrossStaticElems float2 per GPU. Returns its device address on `device`,
+// which must be the current device (looked up once per device).
+constexpr size_t kCrossStaticElems = size_t(64) << 20 >> 3;  // 64 MiB of float2
+constexpr int kMaxDevices = 64;
+hipError_t cross_static_scratch(int device, float2** out);
 hipError_t launch_gcc_samples(const srp_geometry_s* g, const float2* psi, int F, int dtype,
                               void* xi, hipStream_t s);
 int nyquist_workgroups_per_cu(int dtype);  // occupancy of the interpolation kernels

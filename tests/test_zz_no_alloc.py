@@ -1,0 +1,64 @@
+"""The allocation-free cross-spectra entry point (srp_cross_spectra_noalloc).
+
+It stages the per-microphone phasors in the library's static device buffer
+instead of a caller workspace. Its output must equal srp_cross_spectra's bit
+for bit (the same kernels run), on two calls in a row, the second with fewer
+frames and another geometry, so that the buffer's previous contents cannot
+leak into the result; a call whose staging would not fit is refused before
+anything runs.
+"""
+import numpy as np
+import pytest
+
+import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2012_09499_amd as srp  # noqa: E402
+
+
+def _geom(wl):
+    return srp.Geometry(wl.mic_xyz, wl.candidates(), fs=wl.fs, L=wl.L, c=wl.c, n_aux=wl.n_aux)
+
+
+def test_noalloc_cross_spectra_equals_workspace_call():
+    big = WL.make_custom(M=12, J_shape=(6, 5, 4), L=1024, F=300, seed=21)
+    small = WL.make_custom(M=5, J_shape=(4, 4, 3), L=512, F=7, seed=22)
+    for wl in (big, small):
+        g = _geom(wl)
+        fr = torch.from_numpy(wl.frames).cuda()
+        ref = srp.cross_spectra(g, fr)
+        out = torch.full((wl.F, g.P, g.K), complex(7.0, -7.0), dtype=torch.complex64,
+                         device="cuda")
+        srp.cross_spectra_noalloc(g, fr, out)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
+        # the result feeds the rest of the path like the workspace call's
+        m1, pk1 = srp.map_nyquist(g, srp.gcc_samples(g, out))
+        m2, pk2 = srp.map_nyquist(g, srp.gcc_samples(g, ref))
+        torch.cuda.synchronize()
+        assert torch.equal(m1, m2) and torch.equal(pk1, pk2)
+        g.close()
+
+
+def test_noalloc_cross_spectra_rejects_oversize_before_running():
+    # 16 mics, K = 513: 64 MiB hold 1,022 frames of phasors, not 1,100
+    wl = WL.make_custom(M=16, J_shape=(3, 3, 3), L=1024, F=2, seed=23)
+    g = _geom(wl)
+    F = 1100
+    frames = torch.zeros((F, g.M, g.L), dtype=torch.float32, device="cuda")
+    out = torch.full((F, g.P, g.K), complex(3.0, 1.0), dtype=torch.complex64, device="cuda")
+    torch.cuda.synchronize()
+    with pytest.raises(srp.SrpError) as e:
+        srp.cross_spectra_noalloc(g, frames, out)
+    assert e.value.status == srp.SRP_ERR_INVALID_ARG
+    torch.cuda.synchronize()
+    assert bool((out == complex(3.0, 1.0)).all())
+    # the largest batch that fits runs
+    Fmax = (64 << 20) // (8 * g.M * g.K)
+    assert Fmax == 1022
+    ok = srp.cross_spectra_noalloc(g, frames[:Fmax], out[:Fmax])
+    torch.cuda.synchronize()
+    assert bool((ok == 0).all())  # zero frames: PHAT gives psi = 0
+    g.close()
