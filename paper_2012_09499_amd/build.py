@@ -20,7 +20,8 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsrp.so")
 ARCH = "gfx950"
 
-SOURCES = ["srp_api.hip", "k_spectra.hip", "k_gcc.hip", "k_nyquist.hip", "k_conventional.hip",
+SOURCES = ["srp_api.hip", "k_spectra.hip", "k_gcc.hip", "k_nyquist.hip", "k_nyquist_mx.hip",
+           "k_conventional.hip",
            "k_argmax.hip", "k_batched.hip", "k_cached.hip", "k_points.hip"]
 
 COMMON = [

@@ -879,6 +879,8 @@ hipError_t launch_nyquist(const srp_geometry_s* g, const void* xi, int F, int dt
     }
     return hipGetLastError();
   }
+  if ((dtype == SRP_BF16 || dtype == SRP_FP16) && mx2_supported(g))
+    return launch_nyquist_mx2(g, xi, F, dtype, map, keys, s);
   if (dtype == SRP_BF16 || dtype == SRP_FP16) {
     static_assert(kMxWaves * 32 == 256, "256-candidate blocks");
     const int per_cu = g->wg_per_cu[dtype == SRP_BF16 ? 1 : 2];

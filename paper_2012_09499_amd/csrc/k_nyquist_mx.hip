@@ -1,0 +1,446 @@
+// BF16 / FP16 Nyquist-Shannon SRP map (Eq. SRPapprox summed over pairs as in
+// Eq. SRP_T_IFT; cost Eq. SRPapproxcompR) on v_mfma_f32_32x32x16_{bf16,f16}
+// with float32 accumulation:
+//   map[f][i] = 2 sum_p sum_{|n| <= h_p} xi_p(nT) sinc(x_p(i) - n).
+//
+// Layout. A workgroup is 4 waves, one per SIMD, and owns 128 candidates x up
+// to 512 frames. Each wave owns 32 candidates and ALL the workgroup's frames
+// (FT 32-frame tiles, FT <= 16): every weight a lane forms feeds FT matrix-core
+// instructions, and the FT accumulator tiles (16 FT registers per lane, 256 at
+// FT = 16) live in the accumulation registers (one wave per SIMD leaves the
+// SIMD's whole register file to it). One step consumes 16 lags: lane (cl, g)
+// (cl = lane % 32, g = lane / 32) holds lags 8g .. 8g+7 of the step for frame
+// cl of every frame tile (A = samples, one 16-byte LDS read per tile) and for
+// candidate cl (B = weights, formed in registers).
+//
+// Samples. Each lag run (<= 64 lags of one pair window, lagrun records of the
+// geometry) is copied into LDS as [frames][64 lags] with 16-byte global-to-LDS
+// copies issued by all four waves, double-buffered: the next run's copies are
+// in flight while the current run is contracted. 16-byte chunk c of row r is
+// stored at chunk c ^ ((r >> 1) & 7) (16 consecutive rows of a step's read hit
+// 8 different chunk positions per row parity: no bank conflicts). The copy
+// offsets of a lane are fixed for the whole kernel except for one per-run
+// chunk clamp; a chunk past the run repeats the run's last chunk and its
+// weights are zeroed instead (a run's last chunk ends at its window's end, and
+// the columns between the window's end and the chunk's end are the sample
+// layout's zero gap).
+//
+// Weights. x = xi + xf with xi = rint(x) and the fraction xf rounded to the
+// grid 2^-e, e chosen per geometry so that every sinc denominator
+// d = (xi - n) + xf (|d| < 2 h_max + 64) is an exact float32 number; a zero
+// fraction becomes one grid step. This moves x by at most 2^-(e+1) (2^-17 at
+// the room scale), far below a BF16/FP16 unit of the weights. With exact
+// denominators a pair of weights costs one fma for d (d - 1), one reciprocal
+// and three multiplies: with u = d_j, r = qs / (u (u - 1)),
+// w_j = (u - 1) r and w_{j+1} = -u r, qs = (-1)^(xi - n) sin(pi xf) / pi.
+// TDOAs are float64 per pair as in every map kernel.
+#include <cmath>
+#include <type_traits>
+#include <utility>
+
+#include "srp_device.h"
+#include "srp_internal.h"
+
+namespace srp {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+
+template <typename T> struct Mx32;
+template <> struct Mx32<__bf16> {
+  typedef bf16x8 type;
+  static __device__ __forceinline__ floatx16 mfma(bf16x8 a, bf16x8 b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mx32<_Float16> {
+  typedef halfx8 type;
+  static __device__ __forceinline__ floatx16 mfma(halfx8 a, halfx8 b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+constexpr int kWaves = 4;            // one per SIMD
+constexpr int kRow = kNyqRunMax;     // elements per LDS row (64 lags)
+
+struct MxArgs {
+  const double* cand;      // [3][J]
+  int F;
+  int f_base;              // first frame of this launch's frame blocks
+  int64_t j_base;          // first candidate of this launch's candidate blocks
+  int S;
+  int64_t J;
+  int n_runs;
+  double inv_cT;
+  double xq_scale;         // 2^e: the grid of the TDOA fractions
+  int far_field;
+  float* map;              // [F][J] or null
+  unsigned long long* keys;  // peaks viewed as u64 pairs, or null
+};
+
+// Register sets of the sample-read ring: the largest divisor of FT up to 8.
+constexpr int ring_size(int ft) {
+  int r = ft < 8 ? ft : 8;
+  while (ft % r != 0) --r;
+  return r;
+}
+
+// Calls f(integral_constant<int, I>) for I = 0 .. N-1, each call inlined.
+template <typename F, int... I>
+__device__ __forceinline__ void static_for(std::integer_sequence<int, I...>, F&& f) {
+  (f(std::integral_constant<int, I>()), ...);
+}
+
+// Max of v over the 32 lanes of each half-wave (halves separate): butterflies
+// within each row of 16 lanes, then across the two rows of the half.
+__device__ __forceinline__ float half_wave_fmax(float v) {
+#pragma unroll
+  for (int off = 1; off < 32; off <<= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+template <typename T, int FT>
+__global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void nyquist_mx2_kernel(MxArgs a, const T* __restrict__ xi, const RunRec* __restrict__ recs) {
+  typedef typename Mx32<T>::type vec8;
+  typedef __attribute__((address_space(3))) void* lds_ptr;
+  constexpr int FB = 32 * FT;
+  constexpr int JW = 64;                 // candidates per wave: two 32-candidate tiles
+  constexpr int JB = JW * kWaves;
+  constexpr int kTile = 4 * FB * 16;     // elements of a staging tile (4 chunk pairs)
+  __shared__ __attribute__((aligned(16))) T xs0[kTile];
+  __shared__ __attribute__((aligned(16))) T xs1[kTile];
+  __shared__ unsigned long long kbest[FB];
+
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid & 63;
+  const int cl = lane & 31;
+  const int g = lane >> 5;
+  const int64_t jw = a.j_base + (int64_t)blockIdx.x * JB + wave * JW;  // the wave's first candidate
+  const int f0 = a.f_base + blockIdx.y * FB;
+  const int nrows = a.F - f0 < FB ? a.F - f0 : FB;
+
+  // The lane's own candidate is jw + 32 g + cl (tile g): lanes cl and cl + 32
+  // split the TDOAs of the two tiles' candidates cl and exchange them.
+  const int64_t own = jw + 32 * g + cl;
+  const int64_t oc = own < a.J ? own : a.J - 1;
+  const double qx = a.cand[oc], qy = a.cand[a.J + oc], qz = a.cand[2 * a.J + oc];
+  for (int i = tid; i < FB; i += 64 * kWaves) kbest[i] = 0ull;
+
+  // staging: the tile holds, for each pair j of 16-byte chunks (16 lags), the
+  // 32-byte pieces of all FB rows: element (j FB + row) 16 + e. One copy
+  // instruction moves one chunk pair of 32 rows (lane i: row 32 G + i / 2,
+  // chunk 2 j + i % 2), landing as 1 KB of contiguous LDS; wave w copies the
+  // row groups G = w, w + 4, ... Rows at or past F repeat the last frame (their
+  // outputs are discarded); a chunk past the run repeats its last chunk (its
+  // weights are zero). Only the chunk pairs the run's steps read are copied.
+  constexpr int kGroups = FT;                             // 32-row groups of the tile
+  constexpr int kGpw = (kGroups + kWaves - 1) / kWaves;   // groups per wave
+  const int sub = lane & 1;
+  unsigned roff[kGpw];
+#pragma unroll
+  for (int k = 0; k < kGpw; ++k) {
+    const int row = 32 * (wave + kWaves * k) + (lane >> 1);
+    const int rr = row < nrows ? row : nrows - 1;
+    roff[k] = static_cast<unsigned>(rr) * static_cast<unsigned>(a.S) * sizeof(T);
+  }
+  const T* xblk = xi + (size_t)f0 * a.S;
+  auto stage = [&](const RunRec& run, T* tile) __attribute__((always_inline)) {
+    if (run.len <= 0) return;
+    const int nch = (run.len + 7) >> 3;
+    const int npairs = (nch + 1) >> 1;
+    const char* base = reinterpret_cast<const char*>(xblk + run.off + run.t0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (j >= npairs) break;  // (uniform)
+      const int ch = 2 * j + sub < nch ? 2 * j + sub : nch - 1;
+#pragma unroll
+      for (int k = 0; k < kGpw; ++k) {
+        const int G = wave + kWaves * k;
+        if (kGroups % kWaves != 0 && G >= kGroups) break;  // (uniform) no such group
+        __builtin_amdgcn_global_load_lds(
+            reinterpret_cast<const void*>(base + (roff[k] + 16u * static_cast<unsigned>(ch))),
+            (lds_ptr)(tile + (j * FB + 32 * G) * 16), 16, 0, 0);
+      }
+    }
+  };
+
+  floatx16 acc[2][FT];
+#pragma unroll
+  for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[ct][ft][r] = 0.0f;
+
+  // per-pair TDOA split of the two tiles' candidates cl (index 0, 1 = tile)
+  int cur_p = -1, cur_m = -1;
+  double rm = 0.0;
+  int xr[2] = {0, 0};
+  float xf[2] = {0.0f, 0.0f}, sp[2] = {0.0f, 0.0f};
+  auto pair_split = [&](const RunRec& run) __attribute__((always_inline)) {
+    double x;
+    if (a.far_field) {
+      x = ((run.pm[0] - run.pn[0]) * qx + (run.pm[1] - run.pn[1]) * qy +
+           (run.pm[2] - run.pn[2]) * qz) * a.inv_cT;
+    } else {
+      if (run.m != cur_m) {
+        rm = norm3(qx - run.pm[0], qy - run.pm[1], qz - run.pm[2]);
+        cur_m = run.m;
+      }
+      x = (rm - norm3(qx - run.pn[0], qy - run.pn[1], qz - run.pn[2])) * a.inv_cT;
+    }
+    const double r = rint(x);
+    const double fd0 = x - r;
+    double q = rint(fd0 * a.xq_scale);
+    q = q != 0.0 ? q : (fd0 < 0.0 ? -1.0 : 1.0);
+    const double fd = q / a.xq_scale;
+    const int xr_own = static_cast<int>(r);
+    const float xf_own = static_cast<float>(fd);  // exact: a grid point
+    const float sp_own = sinpi_over_pi(fd);
+    const int xr_oth = __shfl_xor(xr_own, 32, 64);
+    const float xf_oth = __shfl_xor(xf_own, 32, 64);
+    const float sp_oth = __shfl_xor(sp_own, 32, 64);
+    xr[0] = g ? xr_oth : xr_own;
+    xr[1] = g ? xr_own : xr_oth;
+    xf[0] = g ? xf_oth : xf_own;
+    xf[1] = g ? xf_own : xf_oth;
+    sp[0] = g ? sp_oth : sp_own;
+    sp[1] = g ? sp_own : sp_oth;
+    cur_p = run.p;
+  };
+
+  // Contracts one staged run. A step's sample fragment of frame tile ft is
+  // row 32 ft + cl of chunk pair s, half g: one 16-byte LDS read (the 64 lanes
+  // together read 1 KB of contiguous LDS), used by the matrix-core
+  // instructions of both candidate tiles.
+  auto contract_run = [&](const RunRec& run, const T* tile) __attribute__((always_inline)) {
+    if (run.len <= 0) return;
+    if (run.p != cur_p) pair_split(run);
+    const int nch = (run.len + 7) >> 3;
+    const int steps = (run.len + 15) >> 4;
+    // d of the lane's first lag in step s for tile ct: (xr + h - t0 - 8g - 16 s)
+    // + xf, exact; the sign (-1)^(xi - n) is the same for all of them
+    float qs[2], u0[2];
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      const int ia = xr[ct] + run.h - run.t0 - 8 * g;
+      qs[ct] = (ia & 1) ? -sp[ct] : sp[ct];
+      u0[ct] = static_cast<float>(ia) + xf[ct];
+    }
+    const T* tbase = tile + cl * 16 + 8 * g;
+    // (steps past the run re-read its last step and are never contracted)
+    auto frag_addr = [&](int s) __attribute__((always_inline)) {
+      const int sc = s < steps ? s : steps - 1;
+      return tbase + sc * (FB * 16);
+    };
+    auto read = [&](const T* src, int ft) __attribute__((always_inline)) {
+      return *reinterpret_cast<const vec8*>(src + ft * 32 * 16);
+    };
+    auto weights = [&](int s, vec8 (&wv)[2]) __attribute__((always_inline)) {
+      // chunks past the run carry weight 0 (their samples repeat the last chunk)
+      const bool live = 2 * s + g < nch;
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) {
+        const float q = live ? qs[ct] : 0.0f;
+        const float ub = u0[ct] - static_cast<float>(16 * s);
+#pragma unroll
+        for (int j = 0; j < 8; j += 2) {
+          const float u = ub - static_cast<float>(j);
+          const float r = q * __builtin_amdgcn_rcpf(fmaf(u, u, -u));
+          wv[ct][j] = static_cast<T>(fmaf(r, u, -r));
+          wv[ct][j + 1] = static_cast<T>(-r * u);
+        }
+      }
+    };
+    // Software pipeline: a ring of kRing sample fragments, the read of
+    // fragment q + kRing issued right after the instructions that consumed
+    // fragment q (the ring size divides FT, so a fragment's slot is the same
+    // in every step); the next step's weights are formed between this step's
+    // matrix-core instructions.
+    constexpr int kRing = ring_size(FT);
+    vec8 ring[kRing];
+    {
+      const T* src = frag_addr(0);
+#pragma unroll
+      for (int i = 0; i < kRing; ++i) ring[i] = read(src, i);
+    }
+    auto step = [&](const vec8 (&wc)[2], const T* cur, const T* nxt) __attribute__((always_inline)) {
+#pragma unroll
+      for (int i = 0; i < FT; ++i) {
+        acc[0][i] = Mx32<T>::mfma(ring[i % kRing], wc[0], acc[0][i]);
+        acc[1][i] = Mx32<T>::mfma(ring[i % kRing], wc[1], acc[1][i]);
+        const int q = i + kRing;  // fragment read into the freed slot
+        ring[i % kRing] = q < FT ? read(cur, q) : read(nxt, q - FT);
+      }
+      // issue order per fragment: a matrix-core instruction, the LDS read
+      // into the slot the fragment frees, vector instructions, the second
+      // matrix-core instruction, vector instructions
+#pragma unroll
+      for (int i = 0; i < FT; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
+      }
+    };
+    // read addresses first (scheduling barriers keep them ahead), then each
+    // step's instructions with the next step's weights slotted between them
+    // (the addresses are recomputed from the tile every iteration rather than
+    // carried across iterations: a pointer that the loop carries hides which
+    // staging buffer it points into, and the compiler then waits for the other
+    // buffer's copies in flight before reading)
+    vec8 w0[2], w1[2];
+    weights(0, w0);
+    int s = 0;
+    for (; s + 1 < steps; s += 2) {
+      const T* p0 = frag_addr(s);
+      const T* p1 = frag_addr(s + 1);
+      const T* p2 = frag_addr(s + 2);
+      __builtin_amdgcn_sched_barrier(0);
+      weights(s + 1, w1);
+      step(w0, p0, p1);
+      __builtin_amdgcn_sched_barrier(0);
+      weights(s + 2, w0);
+      step(w1, p1, p2);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (s < steps) {
+      const T* p0 = frag_addr(s);
+      step(w0, p0, p0);
+    }
+  };
+
+  stage(recs[0], xs0);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  for (int ri = 0; ri < a.n_runs; ri += 2) {
+    // even run: read xs0, copy the next run into xs1; odd run: the other way
+    // round (the run count is even)
+    const RunRec r0 = recs[ri];
+    const RunRec r1 = recs[ri + 1];
+    stage(r1, xs1);
+    contract_run(r0, xs0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (ri + 2 < a.n_runs) stage(recs[ri + 2], xs0);
+    contract_run(r1, xs1);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  }
+
+  // epilogue: D[frame][cand], lane (cl, g), register r -> frame 8 (r / 4) + 4 g + r % 4,
+  // candidate jw + 32 ct + cl. Per frame, the maximum over the wave's 64
+  // candidates, the lowest candidate holding it (tile 0 before tile 1, lower
+  // lanes first), and one LDS max per frame and wave on a (value, -index) key.
+  bool valid[2];
+#pragma unroll
+  for (int ct = 0; ct < 2; ++ct) valid[ct] = jw + 32 * ct + cl < a.J;
+  static_for(std::make_integer_sequence<int, FT>(), [&](auto ftc) __attribute__((always_inline)) {
+    constexpr int ft = decltype(ftc)::value;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int fl = ft * 32 + 8 * (r >> 2) + 4 * g + (r & 3);
+      const int fg = f0 + fl;
+      float vv[2];
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) {
+        const float v = 2.0f * acc[ct][ft][r];
+        if (a.map && valid[ct] && fg < a.F) a.map[(size_t)fg * a.J + jw + 32 * ct + cl] = v;
+        vv[ct] = valid[ct] ? v : -__builtin_inff();
+      }
+      if (a.keys) {
+        const float vmax = half_wave_fmax(fmaxf(vv[0], vv[1]));
+        const unsigned long long h0 = __ballot(vv[0] == vmax);
+        const unsigned long long h1 = __ballot(vv[1] == vmax);
+        const unsigned long long m0 = g ? (h0 >> 32) : (h0 & 0xffffffffull);
+        const unsigned long long m1 = g ? (h1 >> 32) : (h1 & 0xffffffffull);
+        const int first = m0 ? __builtin_ctzll(m0) : 32 + __builtin_ctzll(m1 | (1ull << 63));
+        if (cl == 0 && fg < a.F && vmax > -__builtin_inff())
+          atomicMax(&kbest[fl], peak_key(vmax, static_cast<unsigned>(jw + first)));
+      }
+    }
+  });
+  if (a.keys) {
+    __syncthreads();
+    for (int i = tid; i < FB; i += 64 * kWaves) {
+      const unsigned long long k = kbest[i];
+      if (k && f0 + i < a.F) atomicMax(a.keys + 2 * (size_t)(f0 + i), k);
+    }
+  }
+}
+
+// Frame blocks of up to 8 32-frame tiles: full blocks first, then one launch
+// whose single block has just enough tiles for the remaining frames.
+template <typename Launch>
+void mx2_frame_blocks(int F, const MxArgs& a, Launch&& launch) {
+  constexpr int FTMAX = 8, FB = 32 * FTMAX;
+  const int full = F / FB;
+  const int rem = F - full * FB;
+  const int tiles = (rem + 31) / 32;
+  const int blocks = full + (tiles == FTMAX ? 1 : 0);
+  if (blocks > 0) {
+    MxArgs b = a;
+    b.f_base = 0;
+    launch(std::integral_constant<int, FTMAX>(), b, blocks);
+  }
+  if (tiles == 0 || tiles == FTMAX) return;
+  MxArgs b = a;
+  b.f_base = full * FB;
+  switch (tiles) {
+    case 1: launch(std::integral_constant<int, 1>(), b, 1); break;
+    case 2: launch(std::integral_constant<int, 2>(), b, 1); break;
+    case 3: case 4: launch(std::integral_constant<int, 4>(), b, 1); break;
+    case 5: case 6: launch(std::integral_constant<int, 6>(), b, 1); break;
+    default: launch(std::integral_constant<int, FTMAX>(), b, 1); break;
+  }
+}
+
+}  // namespace
+
+// The grid exponent e of the TDOA fractions: every |d| < 2 h_max + 64 must be
+// a float32 number on the grid 2^-e, i.e. fit 24 significant bits.
+int mx_fraction_grid_exponent(int h_max) {
+  int bits = 0;
+  while ((int64_t(1) << bits) <= 2 * int64_t(h_max) + 64) ++bits;
+  return 24 - bits;
+}
+
+bool mx2_supported(const srp_geometry_s* g) {
+  // 32-bit copy offsets within a frame block of 256 rows of 2-byte samples
+  return (int64_t)256 * g->info.S * 2 < (int64_t(1) << 32) &&
+         mx_fraction_grid_exponent(g->info.h_max) >= 8;
+}
+
+hipError_t launch_nyquist_mx2(const srp_geometry_s* g, const void* xi, int F, int dtype,
+                              float* map, unsigned long long* keys, hipStream_t s) {
+  MxArgs a;
+  a.cand = g->d_cand;
+  a.F = F;
+  a.f_base = 0;
+  a.j_base = 0;
+  a.S = static_cast<int>(g->info.S);
+  a.J = g->info.J;
+  a.n_runs = static_cast<int>(g->nyq_runs.size());
+  a.inv_cT = g->inv_cT;
+  a.xq_scale = std::ldexp(1.0, mx_fraction_grid_exponent(g->info.h_max));
+  a.far_field = g->info.field == SRP_FAR_FIELD;
+  a.map = map;
+  a.keys = keys;
+  const unsigned gx = static_cast<unsigned>((a.J + 64 * kWaves - 1) / (64 * kWaves));
+  mx2_frame_blocks(F, a, [&](auto ft, const MxArgs& b, int fblocks) {
+    const dim3 grid(gx, fblocks), blk(64 * kWaves);
+    if (dtype == SRP_BF16)
+      hipLaunchKernelGGL((nyquist_mx2_kernel<__bf16, decltype(ft)::value>), grid, blk, 0, s, b,
+                         static_cast<const __bf16*>(xi), g->d_nyq_recs);
+    else
+      hipLaunchKernelGGL((nyquist_mx2_kernel<_Float16, decltype(ft)::value>), grid, blk, 0, s,
+                         b, static_cast<const _Float16*>(xi), g->d_nyq_recs);
+  });
+  return hipGetLastError();
+}
+
+}  // namespace srp
