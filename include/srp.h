@@ -188,7 +188,10 @@ srp_status srp_map_conventional(const srp_geometry_t* g, const float* psi, int32
  *          columns after each window must hold zeros, as that layout states
  *          (the interpolation reads the first one with a weight, unmasked)
  *   dtype  SRP_FP32: float32 matrix cores; SRP_BF16 / SRP_FP16: weights and
- *          samples in that type on the matrix cores, float32 accumulation;
+ *          samples in that type on the matrix cores, float32 accumulation,
+ *          the TDOA fraction rounded to a per-geometry grid of at most 2^-8
+ *          (2^-16 at the room scale) on which every sinc denominator is exact
+ *          (SRP_ERR_UNSUPPORTED, nothing enqueued, when S >= 2^23);
  *          SRP_FP64: float64 vector units (an exactness check, not a fast path)
  *   map    device, F x J float32, written; may be NULL if peaks is not
  *   peaks  device, F srp_peak, written; may be NULL if map is not */

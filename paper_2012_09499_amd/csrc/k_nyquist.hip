@@ -28,6 +28,7 @@
 //   epilogue: x2, optional map store, argmax via LDS u64 max + one global atomic per frame.
 #include <type_traits>
 
+#include "launch_split.h"
 #include "srp_device.h"
 #include "srp_internal.h"
 
@@ -444,247 +445,6 @@ void nyquist_f32_kernel(NyqArgs a, const RunRec* __restrict__ recs) {
   }
 }
 
-// ---------------------------------------------------------------------------
-// BF16 / FP16 kernel (v_mfma_f32_32x32x16_{bf16,f16}, float32 accumulation).
-// One step consumes 16 lags: lane (cl, g) holds 8 consecutive lags 8g .. 8g+7
-// of the step, for frame cl (A = samples from LDS) and candidate cl (B =
-// weights). Each wave owns 32 candidates and all 32 * FT frames of the block,
-// so every weight is reused FT times. Weights come in pairs from one
-// reciprocal: with r = 1 / (d_j d_{j+1}),  1/d_j = d_{j+1} r  and
-// 1/d_{j+1} = d_j r. The samples are copied to LDS in 16-byte chunks (the
-// sample layout aligns each pair window to 8 samples); chunk c of row r is
-// stored at chunk c ^ ((r >> 1) & 7). The LDS serves 16 lanes x 16 bytes per
-// cycle over 256 bytes of banks, i.e. two 128-byte rows: rows of equal parity
-// share bank halves, and the swizzle gives the 8 rows of each parity among 16
-// consecutive rows 8 different chunks (measured: 187 B/clk per CU for this read
-// pattern, as for a linear read, against 111 B/clk with c ^ (r & 7)).
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
-
-template <typename T> struct MxVec;
-template <> struct MxVec<__bf16> {
-  typedef bf16x8 type;
-  static __device__ __forceinline__ floatx16 mfma(bf16x8 a, bf16x8 b, floatx16 c) {
-    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
-  }
-};
-template <> struct MxVec<_Float16> {
-  typedef halfx8 type;
-  static __device__ __forceinline__ floatx16 mfma(halfx8 a, halfx8 b, floatx16 c) {
-    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
-  }
-};
-
-constexpr int kRowH = kNyqRunMax;  // elements per LDS row (64 lags, 128 bytes)
-
-// Copies one lag run into the swizzled tile [FB][64]: each instruction moves
-// 8 rows (64 lanes x 16 bytes). Only the first NW = 4 waves copy (one per
-// SIMD; see stage_run); wave w handles the row groups 8w, 8w + 8 NW, ...
-// Straight-line code: rows at or past F repeat the last frame (their outputs
-// are discarded), and chunks past the run are copied from a zeroed buffer, so
-// lags past the run need no weight mask (a run's last chunk ends at a window
-// end, whose padding is zero). With NW even, a lane's logical chunk
-// c = cp ^ ((row >> 1) & 7) is the same in all of its wave's row groups.
-template <typename T, int FB, int NW0>
-__device__ __forceinline__ void stage_run_mx(const T* __restrict__ xi, const float* zero, int S,
-                                             int F, int f0, int nrows, const RunRec& run,
-                                             T* tile, int wave, int lane) {
-  typedef __attribute__((address_space(3))) void* lds_ptr;
-  constexpr int NW = 4;  // copying waves
-  static_assert(NW % 2 == 0, "row groups of a wave must share their swizzle");
-  // row groups per wave; when FB is not a multiple of 8 NW rows (a tail block
-  // of an odd number of 32-frame tiles) the last round of groups is partial
-  constexpr int kGroups = (FB + 8 * NW - 1) / (8 * NW);
-  if (run.len <= 0 || wave >= NW) return;
-  const int nch = (run.len + 7) >> 3;            // 16-byte chunks holding the run
-  const int rsub = lane >> 3;                    // row within the 8-row group
-  const int cp = lane & 7;                       // physical chunk in LDS
-  // the empty asm keeps the compiler from hoisting per-group values out of
-  // the run loop into spilled registers
-  int nr = nrows, w = wave;
-  asm volatile("" : "+s"(nr), "+s"(w));
-  const int c = cp ^ ((((8 * w) >> 1) + (rsub >> 1)) & 7);  // logical chunk stored at cp
-  // branch-free choice between the sample chunk and the zero buffer: a lane
-  // past the run adds nothing to the zero buffer's address
-  const uint64_t za = reinterpret_cast<uint64_t>(zero);
-  const uint64_t keep = c < nch ? ~0ull : 0ull;
-  const uint64_t col = reinterpret_cast<uint64_t>(xi + run.off + run.t0 + 8 * c) - za;
-#pragma unroll
-  for (int k = 0; k < kGroups; ++k) {
-    const int rb = 8 * (w + k * NW);
-    if (FB % (8 * NW) != 0 && rb >= FB) break;  // (uniform) the tile has no such group
-    const int row = rb + rsub;
-    const int rr = row < nr ? row : nr - 1;
-    const uint64_t d = col + (uint64_t)(f0 + rr) * (uint64_t)S * sizeof(T);
-    __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(za + (d & keep)),
-                                     (lds_ptr)(tile + rb * kRowH), 16, 0, 0);
-  }
-}
-
-template <typename T, int FT>
-__device__ __forceinline__ void nyq_run_mx(const NyqArgs& a, const RunRec& run,
-                                           LaneState<1>& st, const T* tile, int cl, int g,
-                                           floatx16 (&acc)[FT]) {
-  typedef typename MxVec<T>::type vec8;
-  if (run.len <= 0) return;
-  const RunRec& pd = run;
-  if (run.p != st.cur_p) pair_setup<1>(a, run, st);
-  // lane's first lag of step 0: n = -h + t0 + 8g;  d_j = (ia - 16 s - j) + xf,
-  // the integer part formed exactly first so that the only rounding is the
-  // final addition of xf (d_j is then never 0, since xf != 0)
-  const int ia = st.xr[0] + pd.h - run.t0 - 8 * g;
-  const float qs = (ia & 1) ? -st.sp[0] : st.sp[0];
-  const float xf = st.xf[0];
-  const int steps = (run.len + 15) >> 4;
-  // chunk 2 s + g of row cl sits at (2 s + g) ^ rowsw = 2 s ^ gsw (2 s is even)
-  const int gsw = g ^ ((cl >> 1) & 7);
-  const T* trow = tile + cl * kRowH;
-  // software pipeline with ping-pong operand sets: the LDS samples and the
-  // weights of the next step are fetched and formed while the matrix cores
-  // work on the current one (steps past the run re-read its last step and are
-  // never contracted)
-  auto fetch = [&](int s, vec8 (&av)[FT], vec8& wv) {
-    const int sc = s < steps ? s : steps - 1;
-    const T* src = trow + 8 * ((2 * sc) ^ gsw);
-#pragma unroll
-    for (int ft = 0; ft < FT; ++ft)
-      av[ft] = *reinterpret_cast<const vec8*>(src + ft * 32 * kRowH);
-    const float base = static_cast<float>(ia - 16 * s);
-    float w[8];
-#pragma unroll
-    for (int j = 0; j < 8; j += 2) {
-      const float d0 = (base - static_cast<float>(j)) + xf;
-      const float d1 = (base - static_cast<float>(j + 1)) + xf;
-      const float qr = qs * __builtin_amdgcn_rcpf(d0 * d1);
-      w[j] = qr * d1;
-      w[j + 1] = -qr * d0;
-    }
-#pragma unroll
-    for (int j = 0; j < 8; ++j) wv[j] = static_cast<T>(w[j]);
-  };
-  auto contract = [&](const vec8 (&av)[FT], const vec8& wv) {
-#pragma unroll
-    for (int ft = 0; ft < FT; ++ft) acc[ft] = MxVec<T>::mfma(av[ft], wv, acc[ft]);
-  };
-  auto order = [&]() {
-    // issue order: one matrix-core instruction, the read address, the next
-    // step's LDS reads, then the weight arithmetic slotted between the
-    // remaining instructions
-    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-    __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
-    __builtin_amdgcn_sched_group_barrier(0x100, FT, 0);
-#pragma unroll
-    for (int i = 1; i < FT; ++i) {
-      __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);
-      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-    }
-  };
-  vec8 a0[FT], a1[FT], w0, w1;
-  fetch(0, a0, w0);
-  int s = 0;
-  for (; s + 1 < steps; s += 2) {
-    fetch(s + 1, a1, w1);
-    contract(a0, w0);
-    order();
-    fetch(s + 2, a0, w0);
-    contract(a1, w1);
-    order();
-  }
-  if (s < steps) contract(a0, w0);
-}
-
-// Waves per workgroup of the BF16/FP16 kernel: every wave of the workgroup
-// uses each staged lag run, so more waves mean fewer copies of the samples
-// per candidate (the copies, not the matrix cores, bound this kernel).
-constexpr int kMxWaves = 8;
-
-template <typename T, int FT>
-__global__ __launch_bounds__(64 * kMxWaves) __attribute__((amdgpu_waves_per_eu(2, 2)))
-void nyquist_mx_kernel(NyqArgs a, const T* __restrict__ xi, const RunRec* __restrict__ recs) {
-  constexpr int NW = kMxWaves;
-  constexpr int FB = 32 * FT;
-  constexpr int JB = NW * 32;
-  __shared__ __attribute__((aligned(16))) T xs0[FB * kRowH];
-  __shared__ __attribute__((aligned(16))) T xs1[FB * kRowH];
-  __shared__ unsigned long long kbest[FB];
-
-  const int tid = threadIdx.x;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int lane = tid & 63;
-  const int cl = lane & 31;
-  const int g = lane >> 5;
-  const int64_t jb = a.j_base + (int64_t)blockIdx.x * JB + wave * 32;
-  const int f0 = a.f_base + blockIdx.y * FB;
-  const int nrows = a.F - f0 < FB ? a.F - f0 : FB;
-
-  LaneState<1> st;
-  {
-    int64_t ci = jb + cl;
-    ci = ci < a.J ? ci : a.J - 1;
-    st.qx[0] = a.cand[ci];
-    st.qy[0] = a.cand[a.J + ci];
-    st.qz[0] = a.cand[2 * a.J + ci];
-    st.rm[0] = 0.0;
-    st.xr[0] = 0;
-    st.xf[0] = 0.0f;
-    st.sp[0] = 0.0f;
-  }
-  st.cur_m = -1;
-  st.cur_p = -1;
-  for (int i = tid; i < FB; i += 64 * NW) kbest[i] = 0ull;
-
-  floatx16 acc[FT];
-#pragma unroll
-  for (int ft = 0; ft < FT; ++ft)
-#pragma unroll
-    for (int r = 0; r < 16; ++r) acc[ft][r] = 0.0f;
-
-  stage_run_mx<T, FB, NW>(xi, a.zero, a.S, a.F, f0, nrows, recs[0], xs0, wave, lane);
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  for (int ri = 0; ri < a.n_runs; ri += 2) {
-    const RunRec r0 = recs[ri];
-    const RunRec r1 = recs[ri + 1];
-    stage_run_mx<T, FB, NW>(xi, a.zero, a.S, a.F, f0, nrows, r1, xs1, wave, lane);
-    nyq_run_mx<T, FT>(a, r0, st, xs0, cl, g, acc);
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if (ri + 2 < a.n_runs)
-      stage_run_mx<T, FB, NW>(xi, a.zero, a.S, a.F, f0, nrows, recs[ri + 2], xs0, wave, lane);
-    nyq_run_mx<T, FT>(a, r1, st, xs1, cl, g, acc);
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-  }
-
-  const int64_t ci = jb + cl;
-#pragma unroll
-  for (int ft = 0; ft < FT; ++ft) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int fl = ft * 32 + 8 * (r >> 2) + 4 * g + (r & 3);
-      const int fg = f0 + fl;
-      unsigned long long best = 0ull;
-      const float v = 2.0f * acc[ft][r];
-      if (ci < a.J && fg < a.F) {
-        if (a.map) a.map[(size_t)fg * a.J + ci] = v;
-        best = peak_key(v, static_cast<unsigned>(ci));
-      }
-      if (a.keys) {
-        best = half_wave_max(best);
-        if (cl == 0 && best) atomicMax(&kbest[fl], best);
-      }
-    }
-  }
-  if (a.keys) {
-    __syncthreads();
-    for (int i = tid; i < FB; i += 64 * NW) {
-      const unsigned long long k = kbest[i];
-      if (k && f0 + i < a.F) atomicMax(a.keys + 2 * (size_t)(f0 + i), k);
-    }
-  }
-}
-
 // Float64 instance (vector units): one thread per candidate, FB64 frames per
 // block. Same data flow as the FP32 kernel; exists to check indexing and
 // algebra against the float64 oracle to ~1e-12.
@@ -751,94 +511,11 @@ __global__ __launch_bounds__(256) void nyquist_f64_kernel(NyqArgs a) {
 
 }  // namespace
 
-// Frame blocks of FTMAX 32-frame tiles, then (if F is not a multiple of the
-// block) one more launch whose single block has just enough tiles for the
-// remaining frames, so no matrix-core work is spent on frames past F.
-template <int FTMAX, typename Launch>
-void launch_frame_blocks(int F, const NyqArgs& a, Launch&& launch) {
-  constexpr int FB = 32 * FTMAX;
-  const int full = F / FB;
-  const int rem = F - full * FB;
-  const int tiles = (rem + 31) / 32;  // 0 .. FTMAX (FTMAX <= 8)
-  // a remainder that needs every tile anyway is one more block of the launch
-  const int blocks = full + (tiles == FTMAX ? 1 : 0);
-  if (blocks > 0) {
-    NyqArgs b = a;
-    b.f_base = 0;
-    launch(std::integral_constant<int, FTMAX>(), b, blocks);
-  }
-  if (tiles == 0 || tiles == FTMAX) return;
-  NyqArgs b = a;
-  b.f_base = full * FB;
-  static_assert(FTMAX <= 8, "tail dispatch covers up to 8 tiles");
-  switch (tiles) {
-    case 1: launch(std::integral_constant<int, 1>(), b, 1); break;
-    case 2: launch(std::integral_constant<int, 2>(), b, 1); break;
-    case 3: launch(std::integral_constant<int, (3 < FTMAX ? 3 : FTMAX)>(), b, 1); break;
-    case 4: launch(std::integral_constant<int, (4 < FTMAX ? 4 : FTMAX)>(), b, 1); break;
-    case 5: launch(std::integral_constant<int, (5 < FTMAX ? 5 : FTMAX)>(), b, 1); break;
-    case 6: launch(std::integral_constant<int, (6 < FTMAX ? 6 : FTMAX)>(), b, 1); break;
-    case 7: launch(std::integral_constant<int, (7 < FTMAX ? 7 : FTMAX)>(), b, 1); break;
-    default: launch(std::integral_constant<int, FTMAX>(), b, 1); break;
-  }
-}
-
-// Launches of a kernel with 256-candidate blocks, per_cu workgroups per CU at
-// a time (as their LDS and registers allow) and all of about the same
-// duration. When the workgroups do not fill a whole number of rounds of the
-// CUs, the last round would leave CUs idle for a whole workgroup's time. So
-// the candidate blocks that fill whole rounds run first (frame blocks of up to
-// 8 tiles), and the rest run in one launch with the shortest frame blocks of
-// which one round holds them all, if those are shorter than the first
-// launch's (their last frame block carries padding rows rather than becoming
-// a launch of its own, which would be another round). launch(ft, args, grid)
-// launches the kernel instance with ft 32-frame tiles per block.
-template <typename Launch>
-void launch_in_rounds(const srp_geometry_s* g, int F, const NyqArgs& a, int per_cu,
-                      Launch&& launch) {
-  constexpr int JB = 256;
-  const int64_t round = (int64_t)g->n_cu * per_cu;
-  const int64_t n_cb = (a.J + JB - 1) / JB;
-  const int64_t n_fb = (F + 255) / 256;
-  const int64_t full_cb = (n_cb * n_fb) / round * round / n_fb;
-  const int64_t rest_cb = n_cb - full_cb;
-  const int ft_main = (F + 31) / 32 < 8 ? (F + 31) / 32 : 8;  // tiles of the first launch's blocks
-  auto rest_fb = [&](int ft) { return (F + 32 * ft - 1) / (32 * ft); };
-  int ft_rest = 0;
-  for (int ft = 1; ft < ft_main && ft_rest == 0; ++ft)
-    if (rest_cb * rest_fb(ft) <= round) ft_rest = ft;
-  const bool split = full_cb > 0 && rest_cb > 0 && ft_rest > 0;
-  const unsigned gx = static_cast<unsigned>(split ? full_cb : n_cb);
-  launch_frame_blocks<8>(F, a, [&](auto ft, const NyqArgs& b, int fblocks) {
-    launch(ft, b, dim3(gx, fblocks));
-  });
-  if (!split) return;
-  NyqArgs b = a;
-  b.j_base = full_cb * JB;
-  const dim3 grid(static_cast<unsigned>(rest_cb), static_cast<unsigned>(rest_fb(ft_rest)));
-  switch (ft_rest) {
-    case 1: launch(std::integral_constant<int, 1>(), b, grid); break;
-    case 2: launch(std::integral_constant<int, 2>(), b, grid); break;
-    case 3: launch(std::integral_constant<int, 3>(), b, grid); break;
-    case 4: launch(std::integral_constant<int, 4>(), b, grid); break;
-    case 5: launch(std::integral_constant<int, 5>(), b, grid); break;
-    case 6: launch(std::integral_constant<int, 6>(), b, grid); break;
-    default: launch(std::integral_constant<int, 7>(), b, grid); break;
-  }
-}
-
 int nyquist_workgroups_per_cu(int dtype) {
+  if (dtype != SRP_FP32) return mx2_workgroups_per_cu(dtype);
   int n = 0;
-  hipError_t e;
-  if (dtype == SRP_FP32)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &n, reinterpret_cast<const void*>(&nyquist_f32_kernel<1, 8, 8, false>), 64 * 8, 0);
-  else if (dtype == SRP_BF16)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &n, reinterpret_cast<const void*>(&nyquist_mx_kernel<__bf16, 8>), 64 * kMxWaves, 0);
-  else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &n, reinterpret_cast<const void*>(&nyquist_mx_kernel<_Float16, 8>), 64 * kMxWaves, 0);
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &n, reinterpret_cast<const void*>(&nyquist_f32_kernel<1, 8, 8, false>), 64 * 8, 0);
   return e == hipSuccess && n > 0 ? n : 1;
 }
 
@@ -879,22 +556,8 @@ hipError_t launch_nyquist(const srp_geometry_s* g, const void* xi, int F, int dt
     }
     return hipGetLastError();
   }
-  if ((dtype == SRP_BF16 || dtype == SRP_FP16) && mx2_supported(g))
+  if (dtype == SRP_BF16 || dtype == SRP_FP16)
     return launch_nyquist_mx2(g, xi, F, dtype, map, keys, s);
-  if (dtype == SRP_BF16 || dtype == SRP_FP16) {
-    static_assert(kMxWaves * 32 == 256, "256-candidate blocks");
-    const int per_cu = g->wg_per_cu[dtype == SRP_BF16 ? 1 : 2];
-    launch_in_rounds(g, F, a, per_cu, [&](auto ft, const NyqArgs& b, dim3 grid) {
-      const dim3 blk(64 * kMxWaves);
-      if (dtype == SRP_BF16)
-        hipLaunchKernelGGL((nyquist_mx_kernel<__bf16, decltype(ft)::value>), grid, blk, 0, s, b,
-                           static_cast<const __bf16*>(xi), g->d_nyq_recs);
-      else
-        hipLaunchKernelGGL((nyquist_mx_kernel<_Float16, decltype(ft)::value>), grid, blk, 0, s, b,
-                           static_cast<const _Float16*>(xi), g->d_nyq_recs);
-    });
-    return hipGetLastError();
-  }
   if (dtype == SRP_FP64) {
     dim3 grid(static_cast<unsigned>((a.J + 255) / 256), (F + kFB64 - 1) / kFB64);
     hipLaunchKernelGGL(nyquist_f64_kernel, grid, dim3(256), 0, s, a);

@@ -38,6 +38,7 @@
 #include <type_traits>
 #include <utility>
 
+#include "launch_split.h"
 #include "srp_device.h"
 #include "srp_internal.h"
 
@@ -61,7 +62,13 @@ template <> struct Mx32<_Float16> {
   }
 };
 
-constexpr int kWaves = 4;            // one per SIMD
+// Launch shape: candidate tiles per wave and waves per workgroup (a multiple
+// of the 4 SIMDs of a CU). One tile per wave and two waves per SIMD: the two
+// waves of a SIMD overlap each other's vector work, waits and barriers with
+// the matrix cores (measured at the room scale: 5.1 ms per call, against 5.6
+// ms for two tiles per wave and one wave per SIMD).
+constexpr int kTiles = 1;
+constexpr int kWavesPerBlock = 8;
 constexpr int kRow = kNyqRunMax;     // elements per LDS row (64 lags)
 
 struct MxArgs {
@@ -74,6 +81,7 @@ struct MxArgs {
   int n_runs;
   double inv_cT;
   double xq_scale;         // 2^e: the grid of the TDOA fractions
+  double xq_inv;           // 2^-e
   int far_field;
   float* map;              // [F][J] or null
   unsigned long long* keys;  // peaks viewed as u64 pairs, or null
@@ -84,6 +92,22 @@ constexpr int ring_size(int ft) {
   int r = ft < 8 ? ft : 8;
   while (ft % r != 0) --r;
   return r;
+}
+
+// sin(pi x) / pi for |x| <= 1/2 in float32: the Taylor series of sin,
+// x sum_k (-1)^k pi^(2k) x^(2k) / (2k+1)!, truncated after x^13 (truncation
+// error below 3e-10), a few float32 units of error. The weights of this kernel
+// are rounded to BF16/FP16, so float32 suffices here (x is exact: a grid point).
+__device__ __forceinline__ float sinpi_over_pi_f32(float x) {
+  const float u = x * x;
+  float p = 0.00014842879f;        //  pi^12 / 13!
+  p = fmaf(p, u, -0.0023460810f);  // -pi^10 / 11!
+  p = fmaf(p, u, 0.026147848f);    //  pi^8 / 9!
+  p = fmaf(p, u, -0.19075182f);    // -pi^6 / 7!
+  p = fmaf(p, u, 0.81174243f);     //  pi^4 / 5!
+  p = fmaf(p, u, -1.6449341f);     // -pi^2 / 3!
+  p = fmaf(p, u, 1.0f);
+  return x * p;
 }
 
 // Calls f(integral_constant<int, I>) for I = 0 .. N-1, each call inlined.
@@ -100,14 +124,16 @@ __device__ __forceinline__ float half_wave_fmax(float v) {
   return v;
 }
 
-template <typename T, int FT>
-__global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(1, 1)))
+template <typename T, int FT, int CT, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4, NW / 4)))
 void nyquist_mx2_kernel(MxArgs a, const T* __restrict__ xi, const RunRec* __restrict__ recs) {
   typedef typename Mx32<T>::type vec8;
   typedef __attribute__((address_space(3))) void* lds_ptr;
+  static_assert(CT == 1 || CT == 2, "one or two candidate tiles per wave");
+  static_assert(NW % 4 == 0, "whole waves per SIMD");
   constexpr int FB = 32 * FT;
-  constexpr int JW = 64;                 // candidates per wave: two 32-candidate tiles
-  constexpr int JB = JW * kWaves;
+  constexpr int JW = 32 * CT;            // candidates per wave
+  constexpr int JB = JW * NW;
   constexpr int kTile = 4 * FB * 16;     // elements of a staging tile (4 chunk pairs)
   __shared__ __attribute__((aligned(16))) T xs0[kTile];
   __shared__ __attribute__((aligned(16))) T xs1[kTile];
@@ -122,33 +148,37 @@ void nyquist_mx2_kernel(MxArgs a, const T* __restrict__ xi, const RunRec* __rest
   const int f0 = a.f_base + blockIdx.y * FB;
   const int nrows = a.F - f0 < FB ? a.F - f0 : FB;
 
-  // The lane's own candidate is jw + 32 g + cl (tile g): lanes cl and cl + 32
-  // split the TDOAs of the two tiles' candidates cl and exchange them.
-  const int64_t own = jw + 32 * g + cl;
+  // The lane's own candidate: with two tiles, jw + 32 g + cl (tile g; lanes cl
+  // and cl + 32 split the TDOAs of the two tiles' candidates cl and exchange
+  // them), with one tile jw + cl.
+  const int64_t own = jw + (CT == 2 ? 32 * g : 0) + cl;
   const int64_t oc = own < a.J ? own : a.J - 1;
   const double qx = a.cand[oc], qy = a.cand[a.J + oc], qz = a.cand[2 * a.J + oc];
-  for (int i = tid; i < FB; i += 64 * kWaves) kbest[i] = 0ull;
+  for (int i = tid; i < FB; i += 64 * NW) kbest[i] = 0ull;
 
   // staging: the tile holds, for each pair j of 16-byte chunks (16 lags), the
   // 32-byte pieces of all FB rows: element (j FB + row) 16 + e. One copy
   // instruction moves one chunk pair of 32 rows (lane i: row 32 G + i / 2,
   // chunk 2 j + i % 2), landing as 1 KB of contiguous LDS; wave w copies the
-  // row groups G = w, w + 4, ... Rows at or past F repeat the last frame (their
+  // row groups G = w, w + NW, ... Rows at or past F repeat the last frame (their
   // outputs are discarded); a chunk past the run repeats its last chunk (its
   // weights are zero). Only the chunk pairs the run's steps read are copied.
   constexpr int kGroups = FT;                             // 32-row groups of the tile
-  constexpr int kGpw = (kGroups + kWaves - 1) / kWaves;   // groups per wave
+  constexpr int kGpw = (kGroups + NW - 1) / NW;           // groups per wave
   const int sub = lane & 1;
   unsigned roff[kGpw];
 #pragma unroll
   for (int k = 0; k < kGpw; ++k) {
-    const int row = 32 * (wave + kWaves * k) + (lane >> 1);
+    const int row = 32 * (wave + NW * k) + (lane >> 1);
     const int rr = row < nrows ? row : nrows - 1;
     roff[k] = static_cast<unsigned>(rr) * static_cast<unsigned>(a.S) * sizeof(T);
   }
   const T* xblk = xi + (size_t)f0 * a.S;
+  // copies of a wave per chunk pair (its row groups)
+  const int gw = kGroups % NW == 0 ? kGpw : (kGroups - wave + NW - 1) / NW;
+  // issues a run's copies; returns how many this wave issued
   auto stage = [&](const RunRec& run, T* tile) __attribute__((always_inline)) {
-    if (run.len <= 0) return;
+    if (run.len <= 0) return 0;
     const int nch = (run.len + 7) >> 3;
     const int npairs = (nch + 1) >> 1;
     const char* base = reinterpret_cast<const char*>(xblk + run.off + run.t0);
@@ -158,28 +188,29 @@ void nyquist_mx2_kernel(MxArgs a, const T* __restrict__ xi, const RunRec* __rest
       const int ch = 2 * j + sub < nch ? 2 * j + sub : nch - 1;
 #pragma unroll
       for (int k = 0; k < kGpw; ++k) {
-        const int G = wave + kWaves * k;
-        if (kGroups % kWaves != 0 && G >= kGroups) break;  // (uniform) no such group
+        const int G = wave + NW * k;
+        if (kGroups % NW != 0 && G >= kGroups) break;  // (uniform) no such group
         __builtin_amdgcn_global_load_lds(
             reinterpret_cast<const void*>(base + (roff[k] + 16u * static_cast<unsigned>(ch))),
             (lds_ptr)(tile + (j * FB + 32 * G) * 16), 16, 0, 0);
       }
     }
+    return npairs * gw;
   };
 
-  floatx16 acc[2][FT];
+  floatx16 acc[CT][FT];
 #pragma unroll
-  for (int ct = 0; ct < 2; ++ct)
+  for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
     for (int ft = 0; ft < FT; ++ft)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[ct][ft][r] = 0.0f;
 
-  // per-pair TDOA split of the two tiles' candidates cl (index 0, 1 = tile)
+  // per-pair TDOA split of the tiles' candidates cl (index = tile)
   int cur_p = -1, cur_m = -1;
   double rm = 0.0;
-  int xr[2] = {0, 0};
-  float xf[2] = {0.0f, 0.0f}, sp[2] = {0.0f, 0.0f};
+  int xr[CT];
+  float xf[CT], sp[CT];
   auto pair_split = [&](const RunRec& run) __attribute__((always_inline)) {
     double x;
     if (a.far_field) {
@@ -196,19 +227,25 @@ void nyquist_mx2_kernel(MxArgs a, const T* __restrict__ xi, const RunRec* __rest
     const double fd0 = x - r;
     double q = rint(fd0 * a.xq_scale);
     q = q != 0.0 ? q : (fd0 < 0.0 ? -1.0 : 1.0);
-    const double fd = q / a.xq_scale;
+    const double fd = q * a.xq_inv;  // exact (a power of two)
     const int xr_own = static_cast<int>(r);
     const float xf_own = static_cast<float>(fd);  // exact: a grid point
-    const float sp_own = sinpi_over_pi(fd);
-    const int xr_oth = __shfl_xor(xr_own, 32, 64);
-    const float xf_oth = __shfl_xor(xf_own, 32, 64);
-    const float sp_oth = __shfl_xor(sp_own, 32, 64);
-    xr[0] = g ? xr_oth : xr_own;
-    xr[1] = g ? xr_own : xr_oth;
-    xf[0] = g ? xf_oth : xf_own;
-    xf[1] = g ? xf_own : xf_oth;
-    sp[0] = g ? sp_oth : sp_own;
-    sp[1] = g ? sp_own : sp_oth;
+    const float sp_own = sinpi_over_pi_f32(xf_own);
+    if (CT == 2) {
+      const int xr_oth = __shfl_xor(xr_own, 32, 64);
+      const float xf_oth = __shfl_xor(xf_own, 32, 64);
+      const float sp_oth = __shfl_xor(sp_own, 32, 64);
+      xr[0] = g ? xr_oth : xr_own;
+      xr[CT - 1] = g ? xr_own : xr_oth;
+      xf[0] = g ? xf_oth : xf_own;
+      xf[CT - 1] = g ? xf_own : xf_oth;
+      sp[0] = g ? sp_oth : sp_own;
+      sp[CT - 1] = g ? sp_own : sp_oth;
+    } else {
+      xr[0] = xr_own;
+      xf[0] = xf_own;
+      sp[0] = sp_own;
+    }
     cur_p = run.p;
   };
 
@@ -223,9 +260,9 @@ void nyquist_mx2_kernel(MxArgs a, const T* __restrict__ xi, const RunRec* __rest
     const int steps = (run.len + 15) >> 4;
     // d of the lane's first lag in step s for tile ct: (xr + h - t0 - 8g - 16 s)
     // + xf, exact; the sign (-1)^(xi - n) is the same for all of them
-    float qs[2], u0[2];
+    float qs[CT], u0[CT];
 #pragma unroll
-    for (int ct = 0; ct < 2; ++ct) {
+    for (int ct = 0; ct < CT; ++ct) {
       const int ia = xr[ct] + run.h - run.t0 - 8 * g;
       qs[ct] = (ia & 1) ? -sp[ct] : sp[ct];
       u0[ct] = static_cast<float>(ia) + xf[ct];
@@ -239,11 +276,11 @@ void nyquist_mx2_kernel(MxArgs a, const T* __restrict__ xi, const RunRec* __rest
     auto read = [&](const T* src, int ft) __attribute__((always_inline)) {
       return *reinterpret_cast<const vec8*>(src + ft * 32 * 16);
     };
-    auto weights = [&](int s, vec8 (&wv)[2]) __attribute__((always_inline)) {
+    auto weights = [&](int s, vec8 (&wv)[CT]) __attribute__((always_inline)) {
       // chunks past the run carry weight 0 (their samples repeat the last chunk)
       const bool live = 2 * s + g < nch;
 #pragma unroll
-      for (int ct = 0; ct < 2; ++ct) {
+      for (int ct = 0; ct < CT; ++ct) {
         const float q = live ? qs[ct] : 0.0f;
         const float ub = u0[ct] - static_cast<float>(16 * s);
 #pragma unroll
@@ -267,11 +304,12 @@ void nyquist_mx2_kernel(MxArgs a, const T* __restrict__ xi, const RunRec* __rest
 #pragma unroll
       for (int i = 0; i < kRing; ++i) ring[i] = read(src, i);
     }
-    auto step = [&](const vec8 (&wc)[2], const T* cur, const T* nxt) __attribute__((always_inline)) {
+    auto step = [&](const vec8 (&wc)[CT], const T* cur, const T* nxt) __attribute__((always_inline)) {
 #pragma unroll
       for (int i = 0; i < FT; ++i) {
-        acc[0][i] = Mx32<T>::mfma(ring[i % kRing], wc[0], acc[0][i]);
-        acc[1][i] = Mx32<T>::mfma(ring[i % kRing], wc[1], acc[1][i]);
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+          acc[ct][i] = Mx32<T>::mfma(ring[i % kRing], wc[ct], acc[ct][i]);
         const int q = i + kRing;  // fragment read into the freed slot
         ring[i % kRing] = q < FT ? read(cur, q) : read(nxt, q - FT);
       }
@@ -283,8 +321,10 @@ void nyquist_mx2_kernel(MxArgs a, const T* __restrict__ xi, const RunRec* __rest
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
         __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
         __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
+        if (CT == 2) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
+        }
       }
     };
     // read addresses first (scheduling barriers keep them ahead), then each
@@ -293,7 +333,7 @@ void nyquist_mx2_kernel(MxArgs a, const T* __restrict__ xi, const RunRec* __rest
     // carried across iterations: a pointer that the loop carries hides which
     // staging buffer it points into, and the compiler then waits for the other
     // buffer's copies in flight before reading)
-    vec8 w0[2], w1[2];
+    vec8 w0[CT], w1[CT];
     weights(0, w0);
     int s = 0;
     for (; s + 1 < steps; s += 2) {
@@ -336,29 +376,34 @@ void nyquist_mx2_kernel(MxArgs a, const T* __restrict__ xi, const RunRec* __rest
   // candidate jw + 32 ct + cl. Per frame, the maximum over the wave's 64
   // candidates, the lowest candidate holding it (tile 0 before tile 1, lower
   // lanes first), and one LDS max per frame and wave on a (value, -index) key.
-  bool valid[2];
+  bool valid[CT];
 #pragma unroll
-  for (int ct = 0; ct < 2; ++ct) valid[ct] = jw + 32 * ct + cl < a.J;
+  for (int ct = 0; ct < CT; ++ct) valid[ct] = jw + 32 * ct + cl < a.J;
   static_for(std::make_integer_sequence<int, FT>(), [&](auto ftc) __attribute__((always_inline)) {
     constexpr int ft = decltype(ftc)::value;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int fl = ft * 32 + 8 * (r >> 2) + 4 * g + (r & 3);
       const int fg = f0 + fl;
-      float vv[2];
+      float vv[CT];
 #pragma unroll
-      for (int ct = 0; ct < 2; ++ct) {
+      for (int ct = 0; ct < CT; ++ct) {
         const float v = 2.0f * acc[ct][ft][r];
         if (a.map && valid[ct] && fg < a.F) a.map[(size_t)fg * a.J + jw + 32 * ct + cl] = v;
         vv[ct] = valid[ct] ? v : -__builtin_inff();
       }
       if (a.keys) {
-        const float vmax = half_wave_fmax(fmaxf(vv[0], vv[1]));
+        const float vmax = half_wave_fmax(CT == 2 ? fmaxf(vv[0], vv[CT - 1]) : vv[0]);
         const unsigned long long h0 = __ballot(vv[0] == vmax);
-        const unsigned long long h1 = __ballot(vv[1] == vmax);
         const unsigned long long m0 = g ? (h0 >> 32) : (h0 & 0xffffffffull);
-        const unsigned long long m1 = g ? (h1 >> 32) : (h1 & 0xffffffffull);
-        const int first = m0 ? __builtin_ctzll(m0) : 32 + __builtin_ctzll(m1 | (1ull << 63));
+        int first;
+        if (CT == 2) {
+          const unsigned long long h1 = __ballot(vv[CT - 1] == vmax);
+          const unsigned long long m1 = g ? (h1 >> 32) : (h1 & 0xffffffffull);
+          first = m0 ? __builtin_ctzll(m0) : 32 + __builtin_ctzll(m1 | (1ull << 63));
+        } else {
+          first = __builtin_ctzll(m0 | (1ull << 63));
+        }
         if (cl == 0 && fg < a.F && vmax > -__builtin_inff())
           atomicMax(&kbest[fl], peak_key(vmax, static_cast<unsigned>(jw + first)));
       }
@@ -366,36 +411,10 @@ void nyquist_mx2_kernel(MxArgs a, const T* __restrict__ xi, const RunRec* __rest
   });
   if (a.keys) {
     __syncthreads();
-    for (int i = tid; i < FB; i += 64 * kWaves) {
+    for (int i = tid; i < FB; i += 64 * NW) {
       const unsigned long long k = kbest[i];
       if (k && f0 + i < a.F) atomicMax(a.keys + 2 * (size_t)(f0 + i), k);
     }
-  }
-}
-
-// Frame blocks of up to 8 32-frame tiles: full blocks first, then one launch
-// whose single block has just enough tiles for the remaining frames.
-template <typename Launch>
-void mx2_frame_blocks(int F, const MxArgs& a, Launch&& launch) {
-  constexpr int FTMAX = 8, FB = 32 * FTMAX;
-  const int full = F / FB;
-  const int rem = F - full * FB;
-  const int tiles = (rem + 31) / 32;
-  const int blocks = full + (tiles == FTMAX ? 1 : 0);
-  if (blocks > 0) {
-    MxArgs b = a;
-    b.f_base = 0;
-    launch(std::integral_constant<int, FTMAX>(), b, blocks);
-  }
-  if (tiles == 0 || tiles == FTMAX) return;
-  MxArgs b = a;
-  b.f_base = full * FB;
-  switch (tiles) {
-    case 1: launch(std::integral_constant<int, 1>(), b, 1); break;
-    case 2: launch(std::integral_constant<int, 2>(), b, 1); break;
-    case 3: case 4: launch(std::integral_constant<int, 4>(), b, 1); break;
-    case 5: case 6: launch(std::integral_constant<int, 6>(), b, 1); break;
-    default: launch(std::integral_constant<int, FTMAX>(), b, 1); break;
   }
 }
 
@@ -411,12 +430,25 @@ int mx_fraction_grid_exponent(int h_max) {
 
 bool mx2_supported(const srp_geometry_s* g) {
   // 32-bit copy offsets within a frame block of 256 rows of 2-byte samples
+  // (S < 2^23)
   return (int64_t)256 * g->info.S * 2 < (int64_t(1) << 32) &&
          mx_fraction_grid_exponent(g->info.h_max) >= 8;
 }
 
+int mx2_workgroups_per_cu(int dtype) {
+  int n = 0;
+  const void* k = dtype == SRP_BF16
+                      ? reinterpret_cast<const void*>(
+                            &nyquist_mx2_kernel<__bf16, 8, kTiles, kWavesPerBlock>)
+                      : reinterpret_cast<const void*>(
+                            &nyquist_mx2_kernel<_Float16, 8, kTiles, kWavesPerBlock>);
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 64 * kWavesPerBlock, 0);
+  return e == hipSuccess && n > 0 ? n : 1;
+}
+
 hipError_t launch_nyquist_mx2(const srp_geometry_s* g, const void* xi, int F, int dtype,
                               float* map, unsigned long long* keys, hipStream_t s) {
+  static_assert(32 * kTiles * kWavesPerBlock == 256, "256-candidate blocks (launch_in_rounds)");
   MxArgs a;
   a.cand = g->d_cand;
   a.F = F;
@@ -427,18 +459,20 @@ hipError_t launch_nyquist_mx2(const srp_geometry_s* g, const void* xi, int F, in
   a.n_runs = static_cast<int>(g->nyq_runs.size());
   a.inv_cT = g->inv_cT;
   a.xq_scale = std::ldexp(1.0, mx_fraction_grid_exponent(g->info.h_max));
+  a.xq_inv = std::ldexp(1.0, -mx_fraction_grid_exponent(g->info.h_max));
   a.far_field = g->info.field == SRP_FAR_FIELD;
   a.map = map;
   a.keys = keys;
-  const unsigned gx = static_cast<unsigned>((a.J + 64 * kWaves - 1) / (64 * kWaves));
-  mx2_frame_blocks(F, a, [&](auto ft, const MxArgs& b, int fblocks) {
-    const dim3 grid(gx, fblocks), blk(64 * kWaves);
+  const int per_cu = g->wg_per_cu[dtype == SRP_BF16 ? 1 : 2];
+  launch_in_rounds(g, F, a, per_cu, [&](auto ft, const MxArgs& b, dim3 grid) {
+    constexpr int FTv = decltype(ft)::value;
+    const dim3 blk(64 * kWavesPerBlock);
     if (dtype == SRP_BF16)
-      hipLaunchKernelGGL((nyquist_mx2_kernel<__bf16, decltype(ft)::value>), grid, blk, 0, s, b,
-                         static_cast<const __bf16*>(xi), g->d_nyq_recs);
+      hipLaunchKernelGGL((nyquist_mx2_kernel<__bf16, FTv, kTiles, kWavesPerBlock>), grid, blk, 0,
+                         s, b, static_cast<const __bf16*>(xi), g->d_nyq_recs);
     else
-      hipLaunchKernelGGL((nyquist_mx2_kernel<_Float16, decltype(ft)::value>), grid, blk, 0, s,
-                         b, static_cast<const _Float16*>(xi), g->d_nyq_recs);
+      hipLaunchKernelGGL((nyquist_mx2_kernel<_Float16, FTv, kTiles, kWavesPerBlock>), grid, blk,
+                         0, s, b, static_cast<const _Float16*>(xi), g->d_nyq_recs);
   });
   return hipGetLastError();
 }

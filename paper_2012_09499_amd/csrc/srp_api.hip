@@ -222,9 +222,11 @@ srp_status srp_geometry(const double* mic_xyz, int32_t M, const double* cand_xyz
     for (int t0 = 0; t0 < W; t0 += run_len)
       g->nyq_runs.push_back(LagRun{p, t0, W - t0 < run_len ? W - t0 : run_len, 0});
   }
-  // the FP32 interpolation kernel consumes runs two at a time: pad with an
-  // empty run of the last pair (no lags, no copy, no pair change)
-  if (g->nyq_runs.size() % 2) g->nyq_runs.push_back(LagRun{P - 1, 2 * (np[P - 1] + n_aux) + 1, 0, 0});
+  // the FP32 interpolation kernel consumes runs two at a time, the BF16/FP16
+  // one three at a time: pad to a multiple of 6 with empty runs of the last
+  // pair (no lags, no copy, no pair change)
+  while (g->nyq_runs.size() % 6)
+    g->nyq_runs.push_back(LagRun{P - 1, 2 * (np[P - 1] + n_aux) + 1, 0, 0});
   for (int p = 0; p < P; ++p)
     for (int k0 = 0; k0 < in.K; k0 += kConvRunBins)
       g->conv_runs.push_back(LagRun{p, k0, in.K - k0 < kConvRunBins ? in.K - k0 : kConvRunBins, 0});
@@ -429,6 +431,8 @@ srp_status srp_map_nyquist(const srp_geometry_t* g, const void* xi, int32_t F, i
                            float* map, srp_peak* peaks, void* stream) {
   srp_status st = check_map_args(g, xi, F, dtype, map, peaks);
   if (st != SRP_OK) return st;
+  if ((dtype == SRP_BF16 || dtype == SRP_FP16) && !mx2_supported(g))
+    return fail(SRP_ERR_UNSUPPORTED, "BF16/FP16 maps need fewer than 2^23 sample columns");
   DeviceGuard dg(g->device);
   if (!dg.ok) return fail(SRP_ERR_DEVICE, "cannot select the geometry's device");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -437,7 +441,6 @@ srp_status srp_map_nyquist(const srp_geometry_t* g, const void* xi, int32_t F, i
   if (e == hipSuccess)
     e = launch_nyquist(g, xi, F, dtype, map, reinterpret_cast<unsigned long long*>(peaks), s);
   if (e == hipSuccess && peaks) e = launch_peaks_finalize(peaks, F, s);
-  if (e == hipErrorNotSupported) return fail(SRP_ERR_UNSUPPORTED, "dtype not supported here");
   if (e != hipSuccess) return device_fail(e, "map_nyquist");
   return SRP_OK;
 }

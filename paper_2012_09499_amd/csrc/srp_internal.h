@@ -123,9 +123,10 @@ hipError_t launch_gcc_samples(const srp_geometry_s* g, const float2* psi, int F,
 int nyquist_workgroups_per_cu(int dtype);  // occupancy of the interpolation kernels
 hipError_t launch_nyquist(const srp_geometry_s* g, const void* xi, int F, int dtype, float* map,
                           unsigned long long* keys, hipStream_t s);
-// BF16/FP16 Nyquist map kernel with 512-frame waves (k_nyquist_mx.hip): the
-// geometries it takes (S < 2^22 columns), and its launch.
+// BF16/FP16 Nyquist map kernel (k_nyquist_mx.hip): the geometries it takes
+// (S < 2^23 columns), its resident workgroups per CU, and its launch.
 bool mx2_supported(const srp_geometry_s* g);
+int mx2_workgroups_per_cu(int dtype);
 hipError_t launch_nyquist_mx2(const srp_geometry_s* g, const void* xi, int F, int dtype,
                               float* map, unsigned long long* keys, hipStream_t s);
 bool conventional_supports(int dtype);  // dtypes srp_map_conventional has a kernel for
