@@ -166,13 +166,32 @@ srp_status srp_cross_spectra_noalloc(const srp_geometry_t* g, const float* frame
 srp_status srp_gcc_samples(const srp_geometry_t* g, const float* psi, int32_t F, int32_t dtype,
                            void* xi, void* stream);
 
+/* Input of the BF16/FP16 conventional map: the cross-spectra weighted by the
+ * bin weights (Eq. SRP_T) and rounded once to the 16-bit type,
+ * out[f][p][k] = (Re, Im) of w_k psi_p(k) for k < K and (0, 0) for
+ * K <= k < Kp, Kp = K rounded up to a multiple of 8 (row-major, 2 values per
+ * bin, 4 P Kp bytes per frame).
+ *   srp_spectra_lowp_bytes  size for F frames; SRP_ERR_UNSUPPORTED for any
+ *                           dtype other than SRP_BF16 / SRP_FP16
+ *   psi                     device, F x P x K complex64 (srp_cross_spectra)
+ *   out                     device, >= srp_spectra_lowp_bytes, 16-byte aligned */
+srp_status srp_spectra_lowp_bytes(const srp_geometry_t* g, int32_t F, int32_t dtype,
+                                  size_t* bytes);
+srp_status srp_spectra_lowp(const srp_geometry_t* g, const float* psi, int32_t F, int32_t dtype,
+                            void* out, size_t out_bytes, void* stream);
+
 /* Conventional SRP map (Eq. SRP_T_IFT with one discrete IFT per candidate,
- * pair and bin, Section 2.4): map[f][i] = 2 sum_p xi_p(dt_p(i)).
- *   psi    device, F x P x K complex64
+ * pair and bin, Section 2.4; cost Eq. SRPomp): map[f][i] = 2 sum_p xi_p(dt_p(i)).
+ *   psi    device: for SRP_FP32 / SRP_FP64, F x P x K complex64 (srp_cross_spectra);
+ *          for SRP_BF16 / SRP_FP16, the weighted rounded spectra of
+ *          srp_spectra_lowp with the same dtype (16-byte aligned)
  *   map    device, F x J float32, written; may be NULL if peaks is not
  *   peaks  device, F srp_peak, written; may be NULL if map is not
- * dtype: SRP_FP32 (float32 matrix cores) or SRP_FP64 (see srp_dtype); any
- * other dtype returns SRP_ERR_UNSUPPORTED before anything is enqueued. */
+ * dtype: SRP_FP32 (float32 matrix cores), SRP_BF16 / SRP_FP16 (matrix cores on
+ * the 16-bit spectra and phasors of the bins, float32 accumulation; phases
+ * from the float64 TDOA reduced mod 1 at every 32-bin run, rotated in float32
+ * within it; SRP_ERR_UNSUPPORTED when 1024 P Kp >= 2^32) or SRP_FP64 (see
+ * srp_dtype). Every refusal happens before anything is enqueued. */
 srp_status srp_map_conventional(const srp_geometry_t* g, const float* psi, int32_t F,
                                 int32_t dtype, float* map, srp_peak* peaks, void* stream);
 

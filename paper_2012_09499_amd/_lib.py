@@ -25,7 +25,7 @@ def sample_torch_dtype(dtype: str):
     return {"fp32": torch.float32, "fp64": torch.float32, "bf16": torch.bfloat16,
             "fp16": torch.float16}[dtype]
 # dtypes srp_map_conventional has a kernel for (others return SRP_ERR_UNSUPPORTED)
-CONVENTIONAL_DTYPES = ("fp32", "fp64")
+CONVENTIONAL_DTYPES = ("fp32", "fp64", "bf16", "fp16")
 
 
 def conventional_supports(dtype: str) -> bool:
@@ -39,7 +39,7 @@ PHAT = 0
 # exported symbols of include/srp.h
 EXPORTS = ("srp_pair_layout", "srp_geometry", "srp_geometry_query", "srp_geometry_destroy",
            "srp_cross_spectra_workspace", "srp_cross_spectra", "srp_cross_spectra_noalloc",
-           "srp_gcc_samples",
+           "srp_gcc_samples", "srp_spectra_lowp_bytes", "srp_spectra_lowp",
            "srp_map_conventional", "srp_map_nyquist", "srp_map_nyquist_batched_workspace",
            "srp_map_nyquist_batched", "srp_nyquist_weights_bytes", "srp_nyquist_weights",
            "srp_map_nyquist_cached", "srp_map_nyquist_points", "srp_argmax", "srp_last_error",
@@ -93,6 +93,8 @@ def lib() -> C.CDLL:
     L.srp_cross_spectra.argtypes = [vp, vp, i32, i32, vp, C.c_size_t, vp, vp]
     L.srp_cross_spectra_noalloc.argtypes = [vp, vp, i32, i32, vp, vp]
     L.srp_gcc_samples.argtypes = [vp, vp, i32, i32, vp, vp]
+    L.srp_spectra_lowp_bytes.argtypes = [vp, i32, i32, C.POINTER(C.c_size_t)]
+    L.srp_spectra_lowp.argtypes = [vp, vp, i32, i32, vp, C.c_size_t, vp]
     L.srp_map_conventional.argtypes = [vp, vp, i32, i32, vp, vp, vp]
     L.srp_map_nyquist.argtypes = [vp, vp, i32, i32, vp, vp, vp]
     L.srp_argmax.argtypes = [vp, i32, i64, vp, vp]
@@ -298,14 +300,45 @@ def map_nyquist(g: Geometry, xi, dtype: str = "fp32", want_map: bool = True,
     return m, pk
 
 
-def map_conventional(g: Geometry, psi, dtype: str = "fp32", want_map: bool = True,
-                     want_peaks: bool = True, map_out=None, peaks_out=None, stream=None):
-    """psi [F][P][K] complex64 -> (map, peaks) (srp_map_conventional)."""
+def spectra_lowp_buffer(g: Geometry, F: int, dtype: str = "bf16", device="cuda"):
+    """An uninitialised [F][P][Kp][2] buffer for spectra_lowp."""
+    import torch
+    n = C.c_size_t(0)
+    _check(lib().srp_spectra_lowp_bytes(g.handle, int(F), DTYPES[dtype], C.byref(n)))
+    Kp = int(n.value) // (4 * F * g.P)
+    return torch.empty((F, g.P, Kp, 2), dtype=sample_torch_dtype(dtype), device=device)
+
+
+def spectra_lowp(g: Geometry, psi, dtype: str = "bf16", out=None, stream=None):
+    """psi [F][P][K] complex64 -> weighted spectra [F][P][Kp][2] in bf16/fp16
+    (srp_spectra_lowp): the input of the BF16/FP16 conventional map."""
     import torch
     _need_cuda(psi, "psi", torch.complex64)
     F = psi.shape[0]
-    if tuple(psi.shape[1:]) != (g.P, g.K):
-        raise ValueError(f"psi must be [F][{g.P}][{g.K}]")
+    if out is None:
+        out = spectra_lowp_buffer(g, F, dtype, psi.device)
+    _need_cuda(out, "spectra", sample_torch_dtype(dtype))
+    if out.dim() != 4 or tuple(out.shape[:2]) != (F, g.P) or out.shape[3] != 2:
+        raise ValueError(f"spectra must be [{F}][{g.P}][Kp][2]")
+    _check(lib().srp_spectra_lowp(g.handle, psi.data_ptr(), F, DTYPES[dtype], out.data_ptr(),
+                                  out.numel() * out.element_size(), _stream_handle(stream)))
+    return out
+
+
+def map_conventional(g: Geometry, psi, dtype: str = "fp32", want_map: bool = True,
+                     want_peaks: bool = True, map_out=None, peaks_out=None, stream=None):
+    """psi [F][P][K] complex64 (FP32/FP64) or the srp_spectra_lowp output
+    [F][P][Kp][2] (BF16/FP16) -> (map, peaks) (srp_map_conventional)."""
+    import torch
+    F = psi.shape[0]
+    if dtype in ("bf16", "fp16"):
+        _need_cuda(psi, "spectra", sample_torch_dtype(dtype))
+        if psi.dim() != 4 or tuple(psi.shape[1:2]) != (g.P,) or psi.shape[3] != 2:
+            raise ValueError(f"BF16/FP16 spectra must be [F][{g.P}][Kp][2] (spectra_lowp)")
+    else:
+        _need_cuda(psi, "psi", torch.complex64)
+        if tuple(psi.shape[1:]) != (g.P, g.K):
+            raise ValueError(f"psi must be [F][{g.P}][{g.K}]")
     m, pk = _map_outputs(g, F, psi.device, want_map, want_peaks, map_out, peaks_out)
     _check(lib().srp_map_conventional(g.handle, psi.data_ptr(), F, DTYPES[dtype],
                                       m.data_ptr() if m is not None else None,

@@ -368,7 +368,9 @@ __global__ __launch_bounds__(256) void conventional_f64_kernel(ConvArgs a) {
 
 }  // namespace
 
-bool conventional_supports(int dtype) { return dtype == SRP_FP32 || dtype == SRP_FP64; }
+bool conventional_supports(int dtype) {
+  return dtype == SRP_FP32 || dtype == SRP_FP64 || dtype == SRP_BF16 || dtype == SRP_FP16;
+}
 
 hipError_t launch_conventional(const srp_geometry_s* g, const float2* psi, int F, int dtype,
                                float* map, unsigned long long* keys, hipStream_t s) {

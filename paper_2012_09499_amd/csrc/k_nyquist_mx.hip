@@ -82,6 +82,7 @@ struct MxArgs {
   double inv_cT;
   double xq_scale;         // 2^e: the grid of the TDOA fractions
   double xq_inv;           // 2^-e
+  double inv_L;            // conventional map: 1 / L (bin k has phase k x fs / L turns)
   int far_field;
   float* map;              // [F][J] or null
   unsigned long long* keys;  // peaks viewed as u64 pairs, or null
@@ -124,12 +125,16 @@ __device__ __forceinline__ float half_wave_fmax(float v) {
   return v;
 }
 
-template <typename T, int FT, int CT, int NW>
+// CONV selects the conventional map (B = phasors of the bins, A = the
+// weighted cross-spectra) instead of the Nyquist map (B = sinc weights of the
+// lags, A = the GCC samples); the rest of the kernel is shared.
+template <typename T, int FT, int CT, int NW, bool CONV>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4, NW / 4)))
 void nyquist_mx2_kernel(MxArgs a, const T* __restrict__ xi, const RunRec* __restrict__ recs) {
   typedef typename Mx32<T>::type vec8;
   typedef __attribute__((address_space(3))) void* lds_ptr;
   static_assert(CT == 1 || CT == 2, "one or two candidate tiles per wave");
+  static_assert(!CONV || CT == 1, "the conventional map uses one candidate tile per wave");
   static_assert(NW % 4 == 0, "whole waves per SIMD");
   constexpr int FB = 32 * FT;
   constexpr int JW = 32 * CT;            // candidates per wave
@@ -206,11 +211,14 @@ void nyquist_mx2_kernel(MxArgs a, const T* __restrict__ xi, const RunRec* __rest
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[ct][ft][r] = 0.0f;
 
-  // per-pair TDOA split of the tiles' candidates cl (index = tile)
+  // per-pair TDOA split of the tiles' candidates cl (index = tile); for the
+  // conventional map the TDOA in samples and the phasors of 1 and 8 bins
   int cur_p = -1, cur_m = -1;
   double rm = 0.0;
   int xr[CT];
   float xf[CT], sp[CT];
+  double xs = 0.0;
+  float r1c = 1.0f, r1s = 0.0f, r8c = 1.0f, r8s = 0.0f;
   auto pair_split = [&](const RunRec& run) __attribute__((always_inline)) {
     double x;
     if (a.far_field) {
@@ -222,6 +230,16 @@ void nyquist_mx2_kernel(MxArgs a, const T* __restrict__ xi, const RunRec* __rest
         cur_m = run.m;
       }
       x = (rm - norm3(qx - run.pn[0], qy - run.pn[1], qz - run.pn[2])) * a.inv_cT;
+    }
+    if (CONV) {
+      // x is the TDOA in samples; phase of bin k: k x / L turns, reduced mod 1
+      // in float64, then rounded to float32 for the rotations
+      xs = x;
+      const double t1 = x * a.inv_L, t8 = 8.0 * t1;
+      sincospif(2.0f * static_cast<float>(t1 - rint(t1)), &r1s, &r1c);
+      sincospif(2.0f * static_cast<float>(t8 - rint(t8)), &r8s, &r8c);
+      cur_p = run.p;
+      return;
     }
     const double r = rint(x);
     const double fd0 = x - r;
@@ -258,14 +276,24 @@ void nyquist_mx2_kernel(MxArgs a, const T* __restrict__ xi, const RunRec* __rest
     if (run.p != cur_p) pair_split(run);
     const int nch = (run.len + 7) >> 3;
     const int steps = (run.len + 15) >> 4;
-    // d of the lane's first lag in step s for tile ct: (xr + h - t0 - 8g - 16 s)
-    // + xf, exact; the sign (-1)^(xi - n) is the same for all of them
+    // Nyquist: d of the lane's first lag in step s for tile ct,
+    // (xr + h - t0 - 8g - 16 s) + xf, exact; the sign (-1)^(xi - n) is the
+    // same for all of them. Conventional: the phasor of the lane's first bin
+    // k0 + 4g (run.h holds k0), from the float64 phase reduced mod 1; each
+    // step then takes 4 consecutive bins (rotations by one bin) and moves on
+    // by 8 bins
     float qs[CT], u0[CT];
+    float pc = 1.0f, ps = 0.0f;
+    if (CONV) {
+      const double t = static_cast<double>(run.h + 4 * g) * xs * a.inv_L;
+      sincospif(2.0f * static_cast<float>(t - rint(t)), &ps, &pc);
+    } else {
 #pragma unroll
-    for (int ct = 0; ct < CT; ++ct) {
-      const int ia = xr[ct] + run.h - run.t0 - 8 * g;
-      qs[ct] = (ia & 1) ? -sp[ct] : sp[ct];
-      u0[ct] = static_cast<float>(ia) + xf[ct];
+      for (int ct = 0; ct < CT; ++ct) {
+        const int ia = xr[ct] + run.h - run.t0 - 8 * g;
+        qs[ct] = (ia & 1) ? -sp[ct] : sp[ct];
+        u0[ct] = static_cast<float>(ia) + xf[ct];
+      }
     }
     const T* tbase = tile + cl * 16 + 8 * g;
     // (steps past the run re-read its last step and are never contracted)
@@ -276,9 +304,28 @@ void nyquist_mx2_kernel(MxArgs a, const T* __restrict__ xi, const RunRec* __rest
     auto read = [&](const T* src, int ft) __attribute__((always_inline)) {
       return *reinterpret_cast<const vec8*>(src + ft * 32 * 16);
     };
+    // (called for s = 0, 1, 2, ... in order: the conventional phasor advances)
     auto weights = [&](int s, vec8 (&wv)[CT]) __attribute__((always_inline)) {
       // chunks past the run carry weight 0 (their samples repeat the last chunk)
       const bool live = 2 * s + g < nch;
+      if (CONV) {
+        // B rows of bin k: (cos theta_k, -sin theta_k) multiply (Re, Im) of the
+        // weighted spectrum: Re[psi e^{j theta}] = Re psi cos - Im psi sin
+        const float z = live ? 1.0f : 0.0f;
+        float c = pc, sn = ps;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          wv[0][2 * j] = static_cast<T>(z * c);
+          wv[0][2 * j + 1] = static_cast<T>(-z * sn);
+          const float c2 = c * r1c - sn * r1s;
+          sn = c * r1s + sn * r1c;
+          c = c2;
+        }
+        const float c8 = pc * r8c - ps * r8s;
+        ps = pc * r8s + ps * r8c;
+        pc = c8;
+        return;
+      }
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
         const float q = live ? qs[ct] : 0.0f;
@@ -439,9 +486,9 @@ int mx2_workgroups_per_cu(int dtype) {
   int n = 0;
   const void* k = dtype == SRP_BF16
                       ? reinterpret_cast<const void*>(
-                            &nyquist_mx2_kernel<__bf16, 8, kTiles, kWavesPerBlock>)
+                            &nyquist_mx2_kernel<__bf16, 8, kTiles, kWavesPerBlock, false>)
                       : reinterpret_cast<const void*>(
-                            &nyquist_mx2_kernel<_Float16, 8, kTiles, kWavesPerBlock>);
+                            &nyquist_mx2_kernel<_Float16, 8, kTiles, kWavesPerBlock, false>);
   const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 64 * kWavesPerBlock, 0);
   return e == hipSuccess && n > 0 ? n : 1;
 }
@@ -460,6 +507,7 @@ hipError_t launch_nyquist_mx2(const srp_geometry_s* g, const void* xi, int F, in
   a.inv_cT = g->inv_cT;
   a.xq_scale = std::ldexp(1.0, mx_fraction_grid_exponent(g->info.h_max));
   a.xq_inv = std::ldexp(1.0, -mx_fraction_grid_exponent(g->info.h_max));
+  a.inv_L = 1.0 / g->info.L;
   a.far_field = g->info.field == SRP_FAR_FIELD;
   a.map = map;
   a.keys = keys;
@@ -468,11 +516,62 @@ hipError_t launch_nyquist_mx2(const srp_geometry_s* g, const void* xi, int F, in
     constexpr int FTv = decltype(ft)::value;
     const dim3 blk(64 * kWavesPerBlock);
     if (dtype == SRP_BF16)
-      hipLaunchKernelGGL((nyquist_mx2_kernel<__bf16, FTv, kTiles, kWavesPerBlock>), grid, blk, 0,
-                         s, b, static_cast<const __bf16*>(xi), g->d_nyq_recs);
+      hipLaunchKernelGGL((nyquist_mx2_kernel<__bf16, FTv, kTiles, kWavesPerBlock, false>), grid,
+                         blk, 0, s, b, static_cast<const __bf16*>(xi), g->d_nyq_recs);
     else
-      hipLaunchKernelGGL((nyquist_mx2_kernel<_Float16, FTv, kTiles, kWavesPerBlock>), grid, blk,
-                         0, s, b, static_cast<const _Float16*>(xi), g->d_nyq_recs);
+      hipLaunchKernelGGL((nyquist_mx2_kernel<_Float16, FTv, kTiles, kWavesPerBlock, false>),
+                         grid, blk, 0, s, b, static_cast<const _Float16*>(xi), g->d_nyq_recs);
+  });
+  return hipGetLastError();
+}
+
+bool conv_mx_supported(const srp_geometry_s* g) {
+  // 32-bit copy offsets within a frame block of 256 rows of 2 P Kp 2-byte values
+  return (int64_t)256 * 2 * g->info.P * g->Kp * 2 < (int64_t(1) << 32);
+}
+
+int conv_mx_workgroups_per_cu(int dtype) {
+  int n = 0;
+  const void* k = dtype == SRP_BF16
+                      ? reinterpret_cast<const void*>(
+                            &nyquist_mx2_kernel<__bf16, 8, 1, kWavesPerBlock, true>)
+                      : reinterpret_cast<const void*>(
+                            &nyquist_mx2_kernel<_Float16, 8, 1, kWavesPerBlock, true>);
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 64 * kWavesPerBlock, 0);
+  return e == hipSuccess && n > 0 ? n : 1;
+}
+
+// Conventional map in BF16/FP16 on the same skeleton: the runs are 32-bin runs
+// of each pair over the weighted, rounded spectra [F][P][Kp] x (re, im)
+// (srp_spectra_lowp), a frame row holding 2 P Kp values.
+hipError_t launch_conventional_mx(const srp_geometry_s* g, const void* spec, int F, int dtype,
+                                  float* map, unsigned long long* keys, hipStream_t s) {
+  static_assert(kTiles == 1, "256-candidate blocks");
+  MxArgs a;
+  a.cand = g->d_cand;
+  a.F = F;
+  a.f_base = 0;
+  a.j_base = 0;
+  a.S = 2 * g->info.P * g->Kp;
+  a.J = g->info.J;
+  a.n_runs = g->n_convmx_runs;
+  a.inv_cT = g->fs_over_c;  // path difference (m) -> TDOA in samples
+  a.xq_scale = 1.0;
+  a.xq_inv = 1.0;
+  a.inv_L = 1.0 / g->info.L;
+  a.far_field = g->info.field == SRP_FAR_FIELD;
+  a.map = map;
+  a.keys = keys;
+  const int per_cu = g->wg_per_cu_conv[dtype == SRP_BF16 ? 0 : 1];
+  launch_in_rounds(g, F, a, per_cu, [&](auto ft, const MxArgs& b, dim3 grid) {
+    constexpr int FTv = decltype(ft)::value;
+    const dim3 blk(64 * kWavesPerBlock);
+    if (dtype == SRP_BF16)
+      hipLaunchKernelGGL((nyquist_mx2_kernel<__bf16, FTv, 1, kWavesPerBlock, true>), grid, blk,
+                         0, s, b, static_cast<const __bf16*>(spec), g->d_convmx_recs);
+    else
+      hipLaunchKernelGGL((nyquist_mx2_kernel<_Float16, FTv, 1, kWavesPerBlock, true>), grid,
+                         blk, 0, s, b, static_cast<const _Float16*>(spec), g->d_convmx_recs);
   });
   return hipGetLastError();
 }

@@ -72,7 +72,41 @@ __global__ __launch_bounds__(256) void cross_kernel(const float2* __restrict__ y
   psi[fp * K + k] = make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
 }
 
+// Weighted cross-spectra for the BF16/FP16 conventional map: row (f, p) of
+// Kp bins, value k = w_k psi_p(k) for k < K and 0 above, (re, im) rounded once
+// to T. One thread per bin.
+template <typename T>
+__global__ __launch_bounds__(256) void spectra_lowp_kernel(const float2* __restrict__ psi,
+                                                           const float* __restrict__ binw, int K,
+                                                           int Kp, T* __restrict__ out) {
+  const size_t row = blockIdx.x;  // f * P + p
+  const int k = blockIdx.y * blockDim.x + threadIdx.x;
+  if (k >= Kp) return;
+  float2 v = make_float2(0.0f, 0.0f);
+  if (k < K) {
+    const float2 z = psi[row * K + k];
+    const float w = binw[k];
+    v = make_float2(w * z.x, w * z.y);
+  }
+  T* o = out + (row * Kp + k) * 2;
+  o[0] = static_cast<T>(v.x);
+  o[1] = static_cast<T>(v.y);
+}
+
 }  // namespace
+
+hipError_t launch_spectra_lowp(const srp_geometry_s* g, const float2* psi, int F, int dtype,
+                               void* out, hipStream_t s) {
+  const size_t rows = (size_t)F * g->info.P;
+  const dim3 grid(static_cast<unsigned>(rows), (g->Kp + 255) / 256);
+  if (dtype == SRP_BF16)
+    hipLaunchKernelGGL(spectra_lowp_kernel<__bf16>, grid, dim3(256), 0, s, psi, g->d_binw,
+                       g->info.K, g->Kp, static_cast<__bf16*>(out));
+  else
+    hipLaunchKernelGGL(spectra_lowp_kernel<_Float16>, grid, dim3(256), 0, s, psi, g->d_binw,
+                       g->info.K, g->Kp, static_cast<_Float16*>(out));
+  return hipGetLastError();
+}
 
 hipError_t launch_fft_phat(const srp_geometry_s* g, const float* frames, int F, float2* ytil,
                            hipStream_t s) {

@@ -102,6 +102,7 @@ void free_geometry(srp_geometry_s* g) {
   hipFree(g->d_gcc_tiles);
   hipFree(g->d_nyq_runs);
   hipFree(g->d_nyq_recs);
+  hipFree(g->d_convmx_recs);
   hipFree(g->d_conv_runs);
   hipFree(g->d_window);
   hipFree(g->d_twiddle);
@@ -284,6 +285,8 @@ srp_status srp_geometry(const double* mic_xyz, int32_t M, const double* cand_xyz
     g->wg_per_cu[0] = nyquist_workgroups_per_cu(SRP_FP32);
     g->wg_per_cu[1] = nyquist_workgroups_per_cu(SRP_BF16);
     g->wg_per_cu[2] = nyquist_workgroups_per_cu(SRP_FP16);
+    g->wg_per_cu_conv[0] = conv_mx_workgroups_per_cu(SRP_BF16);
+    g->wg_per_cu_conv[1] = conv_mx_workgroups_per_cu(SRP_FP16);
   }
   if (e == hipSuccess) e = upload(&g->d_mic, mic_xyz, 3 * (size_t)M, s);
   if (e == hipSuccess) e = upload(&g->d_cand, cand_soa.data(), cand_soa.size(), s);
@@ -309,6 +312,36 @@ srp_status srp_geometry(const double* mic_xyz, int32_t M, const double* cand_xyz
     }
   }
   if (e == hipSuccess) e = upload(&g->d_nyq_recs, recs.data(), recs.size(), s);
+  // 32-bin runs of the BF16/FP16 conventional map over the weighted spectra
+  // [F][P][Kp] x (re, im): a run's values start at 2 (p Kp + k0) of a frame row
+  g->Kp = (in.K + 7) / 8 * 8;
+  std::vector<RunRec> crecs;
+  for (int p = 0; p < P; ++p) {
+    const PairDesc& pd = g->pairs[p];
+    for (int k0 = 0; k0 < g->Kp; k0 += kConvRunBins) {
+      RunRec q;
+      q.p = p;
+      q.t0 = 2 * k0;
+      q.len = 2 * (g->Kp - k0 < kConvRunBins ? g->Kp - k0 : kConvRunBins);
+      q.off = 2 * p * g->Kp;
+      q.h = k0;
+      q.m = pd.m;
+      q.mp = pd.mp;
+      q.pad = 0;
+      for (int d = 0; d < 3; ++d) {
+        q.pm[d] = mic_xyz[3 * pd.m + d];
+        q.pn[d] = mic_xyz[3 * pd.mp + d];
+      }
+      crecs.push_back(q);
+    }
+  }
+  if (crecs.size() % 2) {  // consumed two at a time: an empty run of the last pair
+    RunRec q = crecs.back();
+    q.len = 0;
+    crecs.push_back(q);
+  }
+  g->n_convmx_runs = static_cast<int>(crecs.size());
+  if (e == hipSuccess) e = upload(&g->d_convmx_recs, crecs.data(), crecs.size(), s);
   if (e == hipSuccess) e = upload(&g->d_conv_runs, g->conv_runs.data(), g->conv_runs.size(), s);
   if (e == hipSuccess) e = upload(&g->d_window, win.data(), win.size(), s);
   if (e == hipSuccess) e = upload(&g->d_twiddle, tw.data(), tw.size(), s);
@@ -416,6 +449,33 @@ srp_status srp_gcc_samples(const srp_geometry_t* g, const float* psi, int32_t F,
   return SRP_OK;
 }
 
+srp_status srp_spectra_lowp_bytes(const srp_geometry_t* g, int32_t F, int32_t dtype,
+                                  size_t* bytes) {
+  if (g == nullptr || bytes == nullptr) return fail(SRP_ERR_INVALID_ARG, "NULL argument");
+  if (F < 1) return fail(SRP_ERR_INVALID_ARG, "F must be >= 1");
+  if (dtype != SRP_BF16 && dtype != SRP_FP16)
+    return fail(SRP_ERR_UNSUPPORTED, "low-precision spectra are BF16 or FP16");
+  *bytes = (size_t)F * g->info.P * g->Kp * 2 * 2;
+  return SRP_OK;
+}
+
+srp_status srp_spectra_lowp(const srp_geometry_t* g, const float* psi, int32_t F, int32_t dtype,
+                            void* out, size_t out_bytes, void* stream) {
+  size_t need = 0;
+  srp_status st = srp_spectra_lowp_bytes(g, F, dtype, &need);
+  if (st != SRP_OK) return st;
+  if (psi == nullptr || out == nullptr) return fail(SRP_ERR_INVALID_ARG, "NULL argument");
+  if (out_bytes < need) return fail(SRP_ERR_INVALID_ARG, "output buffer too small");
+  if ((reinterpret_cast<uintptr_t>(out) & 15) != 0)
+    return fail(SRP_ERR_INVALID_ARG, "output must be 16-byte aligned");
+  DeviceGuard dg(g->device);
+  if (!dg.ok) return fail(SRP_ERR_DEVICE, "cannot select the geometry's device");
+  hipError_t e = launch_spectra_lowp(g, reinterpret_cast<const float2*>(psi), F, dtype, out,
+                                     static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return device_fail(e, "spectra_lowp");
+  return SRP_OK;
+}
+
 static srp_status check_map_args(const srp_geometry_t* g, const void* in, int32_t F,
                                  int32_t dtype, float* map, srp_peak* peaks) {
   if (g == nullptr || in == nullptr) return fail(SRP_ERR_INVALID_ARG, "NULL argument");
@@ -514,14 +574,21 @@ srp_status srp_map_conventional(const srp_geometry_t* g, const float* psi, int32
   // initialised, so an unsupported call writes nothing
   if (!conventional_supports(dtype))
     return fail(SRP_ERR_UNSUPPORTED, "srp_map_conventional: dtype not supported");
+  if ((dtype == SRP_BF16 || dtype == SRP_FP16) && !conv_mx_supported(g))
+    return fail(SRP_ERR_UNSUPPORTED, "BF16/FP16 conventional maps need 256 x 4 P Kp < 2^32 bytes");
   DeviceGuard dg(g->device);
   if (!dg.ok) return fail(SRP_ERR_DEVICE, "cannot select the geometry's device");
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = hipSuccess;
   if (peaks) e = launch_peaks_init(peaks, F, s);
-  if (e == hipSuccess)
-    e = launch_conventional(g, reinterpret_cast<const float2*>(psi), F, dtype, map,
-                            reinterpret_cast<unsigned long long*>(peaks), s);
+  if (e == hipSuccess) {
+    if (dtype == SRP_BF16 || dtype == SRP_FP16)
+      e = launch_conventional_mx(g, psi, F, dtype, map,
+                                 reinterpret_cast<unsigned long long*>(peaks), s);
+    else
+      e = launch_conventional(g, reinterpret_cast<const float2*>(psi), F, dtype, map,
+                              reinterpret_cast<unsigned long long*>(peaks), s);
+  }
   if (e == hipSuccess && peaks) e = launch_peaks_finalize(peaks, F, s);
   if (e != hipSuccess) return device_fail(e, "map_conventional");
   return SRP_OK;

@@ -76,6 +76,9 @@ struct srp_geometry_s {
   int device = 0;
   int n_cu = 256;          // compute units of the device (workgroup rounds)
   int wg_per_cu[3] = {1, 1, 1};  // resident Nyquist workgroups per CU: FP32, BF16, FP16
+  int wg_per_cu_conv[2] = {1, 1};  // resident BF16/FP16 conventional workgroups per CU
+  int Kp = 0;              // bins of a row of the BF16/FP16 conventional input (K up to a multiple of 8)
+  int n_convmx_runs = 0;   // 32-bin runs of the BF16/FP16 conventional map (even count)
   double inv_cT = 0.0;     // converts a path difference in metres into x = dt / T
   double fs_over_c = 0.0;  // converts a path difference in metres into samples
   int log2L = 0;
@@ -93,6 +96,7 @@ struct srp_geometry_s {
   srp::LagRun* d_gcc_tiles = nullptr;
   srp::LagRun* d_nyq_runs = nullptr;
   srp::RunRec* d_nyq_recs = nullptr;   // one record per entry of nyq_runs
+  srp::RunRec* d_convmx_recs = nullptr;  // 32-bin runs of the BF16/FP16 conventional map
   srp::LagRun* d_conv_runs = nullptr;
   float* d_window = nullptr;           // [L]
   float2* d_twiddle = nullptr;         // [L/2] exp(-j 2 pi t / L)
@@ -127,6 +131,15 @@ hipError_t launch_nyquist(const srp_geometry_s* g, const void* xi, int F, int dt
 // (S < 2^23 columns), its resident workgroups per CU, and its launch.
 bool mx2_supported(const srp_geometry_s* g);
 int mx2_workgroups_per_cu(int dtype);
+// BF16/FP16 conventional map on the same kernel (k_nyquist_mx.hip): the
+// geometries it takes (256 x 2 P Kp x 2 bytes < 2^32), occupancy, launch; and
+// the weighted, rounded spectra it reads (k_spectra.hip).
+bool conv_mx_supported(const srp_geometry_s* g);
+int conv_mx_workgroups_per_cu(int dtype);
+hipError_t launch_conventional_mx(const srp_geometry_s* g, const void* spec, int F, int dtype,
+                                  float* map, unsigned long long* keys, hipStream_t s);
+hipError_t launch_spectra_lowp(const srp_geometry_s* g, const float2* psi, int F, int dtype,
+                               void* out, hipStream_t s);
 hipError_t launch_nyquist_mx2(const srp_geometry_s* g, const void* xi, int F, int dtype,
                               float* map, unsigned long long* keys, hipStream_t s);
 bool conventional_supports(int dtype);  // dtypes srp_map_conventional has a kernel for

@@ -1,7 +1,8 @@
 """Frame-batch pipeline over the C ABI with preallocated device buffers.
 
 Nyquist path: srp_cross_spectra -> srp_gcc_samples -> srp_map_nyquist.
-Conventional path: srp_cross_spectra -> srp_map_conventional.
+Conventional path: srp_cross_spectra -> srp_map_conventional (BF16/FP16:
+srp_cross_spectra -> srp_spectra_lowp -> srp_map_conventional).
 Every step is a libsrp kernel; buffers are torch tensors allocated once.
 The map and peaks returned by `nyquist` and `conventional` are views of the
 pipeline's own buffers: the next call overwrites them, so copy a result out
@@ -22,6 +23,7 @@ class SrpPipeline:
         self.device = device
         self.xi = torch.empty((F, geom.S), dtype=torch.float32, device=device)
         self._xi_lowp = {}
+        self._spec_lowp = {}
         self.peaks = torch.empty((F, 2), dtype=torch.int64, device=device)
         self.map = (torch.empty((F, geom.J), dtype=torch.float32, device=device)
                     if keep_map else None)
@@ -59,6 +61,11 @@ class SrpPipeline:
     def conventional(self, frames, dtype: str = "fp32"):
         F = frames.shape[0]
         psi = self.spectra(frames)
+        if dtype in ("bf16", "fp16"):
+            if dtype not in self._spec_lowp:
+                self._spec_lowp[dtype] = S.spectra_lowp_buffer(self.g, self.F, dtype,
+                                                               self.device)
+            psi = S.spectra_lowp(self.g, psi, dtype, out=self._spec_lowp[dtype][:F])
         return S.map_conventional(self.g, psi, dtype=dtype, want_map=self.map is not None,
                                   map_out=None if self.map is None else self.map[:F],
                                   peaks_out=self.peaks[:F])

@@ -486,3 +486,73 @@ def test_conventional_unsupported_dtype_writes_nothing(cases):
     assert st == srp.SRP_ERR_INVALID_ARG
     torch.cuda.synchronize()
     assert bool((pk == -12345).all()) and bool((m == 7.0).all())
+
+
+def _weighted_lowp(wl, g, psi, tdt):
+    """The oracle's cross-spectra weighted by the bin weights and rounded once to
+    the storage type, in the [F][P][Kp][2] layout of the BF16/FP16 conventional
+    map; returns (device tensor, the values as psi again (rounded w psi / w))."""
+    K, w, _ = R.oracle_setup(wl)
+    F, P, _ = psi.shape
+    Kp = (K + 7) // 8 * 8
+    z = np.zeros((F, P, Kp, 2))
+    z[:, :, :K, 0] = (psi * w).real
+    z[:, :, :K, 1] = (psi * w).imag
+    zr = R.rounded(z, tdt)
+    back = (zr[:, :, :K, 0] + 1j * zr[:, :, :K, 1]) / w  # w in {1, 2}: exact
+    return torch.from_numpy(z).to(tdt).cuda(), back
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("dtype", ["bf16", "fp16"])
+def test_spectra_lowp_is_rounded_weighted_psi(cases, name, dtype):
+    """srp_spectra_lowp from the oracle's cross-spectra (rounded to complex64)
+    equals w_k psi rounded once to the storage type, bit for bit, zeros past K."""
+    wl = cases[name]
+    g = _geom(wl)
+    psi_dev, psi_in = R.device_psi(R.oracle_psi(wl))
+    got = srp.spectra_lowp(g, psi_dev, dtype)
+    torch.cuda.synchronize()
+    K, w, _ = R.oracle_setup(wl)
+    ref = torch.zeros(got.shape, dtype=torch.float32)
+    p32 = torch.from_numpy(psi_in.astype(np.complex64))
+    w32 = torch.from_numpy(w.astype(np.float32))
+    ref[:, :, :K, 0] = p32.real * w32
+    ref[:, :, :K, 1] = p32.imag * w32
+    assert torch.equal(got.cpu(), ref.to(got.dtype))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("dtype", ["bf16", "fp16"])
+def test_conventional_lowp_map_kernel(cases, name, dtype):
+    """The BF16/FP16 conventional kernel alone: the oracle's weighted spectra
+    rounded to the storage type feed the kernel and the oracle's map."""
+    wl = cases[name]
+    g = _geom(wl)
+    spec, psi_in = _weighted_lowp(wl, g, R.oracle_psi(wl), srp.sample_torch_dtype(dtype))
+    m, pk = srp.map_conventional(g, spec, dtype=dtype)
+    torch.cuda.synchronize()
+    ref = R.oracle_conventional(wl, psi_in, wl.candidates())
+    got = m.cpu().numpy().astype(np.float64)
+    assert np.all(np.isfinite(got))
+    assert _rel(got, ref).max() <= LOWP_TOL
+    idx = srp.decode_peaks(pk)[0]
+    np.testing.assert_array_equal(idx, np.argmax(got, axis=1))
+    R.check_argmax(idx, ref, LOWP_TOL, label=f"conventional-kernel/{name}/{dtype}")
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("dtype", ["bf16", "fp16"])
+def test_conventional_lowp_pipeline(cases, name, dtype):
+    """Frames -> BF16/FP16 conventional map against the FP64 oracle of the frames."""
+    wl = cases[name]
+    g = _geom(wl)
+    pipe = srp.SrpPipeline(g, wl.F, keep_map=True)
+    m, pk = pipe.conventional(_frames(wl), dtype=dtype)
+    torch.cuda.synchronize()
+    ref = R.oracle_conventional(wl, R.oracle_psi(wl), wl.candidates())
+    got = m.cpu().numpy().astype(np.float64)
+    assert _rel(got, ref).max() <= LOWP_TOL
+    idx = srp.decode_peaks(pk)[0]
+    np.testing.assert_array_equal(idx, np.argmax(got, axis=1))
+    R.check_argmax(idx, ref, LOWP_TOL, label=f"pipeline-conventional/{name}/{dtype}")
