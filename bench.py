@@ -57,36 +57,137 @@ def load_traffic(workload: str):
     return t.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(wl, n_cand: int, seed: int = 0):
-    """The FP64 oracle on a bounded sample: all frames, a seeded candidate subset."""
-    import oracle as O
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _blas_threads() -> int:
     try:
         from threadpoolctl import threadpool_info
-        blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()
-                            if i.get("user_api") == "blas"] or [1])
+        return max([i.get("num_threads", 1) for i in threadpool_info()
+                    if i.get("user_api") == "blas"] or [1])
     except Exception:
-        blas_threads = 1
+        return 1
+
+
+def _oracle_map(O, wl, xi, win, idx, workers, chunk=4096):
+    """The oracle's Nyquist map at candidates idx, in candidate chunks spread over
+    `workers` threads with one BLAS thread each (workers = 1: one thread)."""
+    import concurrent.futures as cf
+    from threadpoolctl import threadpool_limits
+    out = np.empty((xi.shape[0], idx.size))
+
+    def run(j0):
+        j1 = min(idx.size, j0 + chunk)
+        dt = O.tdoa(wl.mic_xyz, wl.candidates_at(idx[j0:j1]), wl.c)
+        out[:, j0:j1] = O.srp_nyquist(xi, dt, win)
+
+    with threadpool_limits(1):
+        if workers == 1:
+            for j0 in range(0, idx.size, chunk):
+                run(j0)
+        else:
+            with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+                list(ex.map(run, range(0, idx.size, chunk)))
+    return out
+
+
+def cpu_baseline(wl, n_cand: int, n_cand_single: int, reps: int = 3, full_argmax: bool = True,
+                 seed: int = 0):
+    """The FP64 oracle timed on the host: spectra, PHAT, GCC samples and the
+    Nyquist map of a seeded candidate sample over all frames, once on one
+    thread and once on all cores (threads over candidate chunks, one BLAS
+    thread each), the median of `reps` runs each; then (untimed for the rate)
+    the oracle's map over ALL candidates, whose per-frame argmax the GPU paths
+    are compared with. Returns (info, sample indices, sample map, full argmax)."""
+    import oracle as O
+    workers = min(16, os.cpu_count() or 1)
     rng = np.random.default_rng(seed)
     idx = np.sort(rng.choice(wl.J, size=min(n_cand, wl.J), replace=False))
-    cand = wl.candidates_at(idx)
-    t0 = time.perf_counter()
+    idx1 = idx[:min(n_cand_single, idx.size)]
     K = O.n_bins(wl.L, wl.fs)
     w = O.bin_weights(wl.L, K)
     win = O.pair_windows(wl.mic_xyz, wl.c, wl.fs / 2, wl.n_aux)
-    psi = O.phat_cross_spectra(O.spectra(wl.frames, O.window(wl.L), K))
+
+    def front():
+        psi = O.phat_cross_spectra(O.spectra(wl.frames, O.window(wl.L), K))
+        return O.gcc_samples(psi, wl.fs, wl.L, w, win)
+
+    from threadpoolctl import threadpool_limits
+    legs = {}
+    ref = None
+    for name, sel, nw in (("single_thread", idx1, 1), ("all_cores", idx, workers)):
+        t_front, t_map = [], []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            with threadpool_limits(1 if nw == 1 else None):
+                xi = front()
+            t1 = time.perf_counter()
+            m = _oracle_map(O, wl, xi, win, sel, nw)
+            O.peaks(m)
+            t2 = time.perf_counter()
+            t_front.append(t1 - t0)
+            t_map.append(t2 - t1)
+        tf, tm = float(np.median(t_front)), float(np.median(t_map))
+        pairs = wl.F * sel.size * wl.P
+        legs[name] = {"value": pairs / (tf + tm), "unit": "cand-pair evals/s",
+                      "map_only_value": pairs / tm, "threads": nw,
+                      "front_end_seconds_median": tf, "map_seconds_median": tm,
+                      "front_end_seconds": t_front, "map_seconds": t_map,
+                      "candidates": int(sel.size), "frames": wl.F}
+        if name == "all_cores":
+            ref = m
+    full = None
+    predicted = legs["all_cores"]["map_seconds_median"] * wl.J / idx.size
+    if full_argmax and predicted > 180.0:
+        full_argmax = False
+        legs["full_map_skipped"] = f"predicted {predicted:.0f} s on {workers} threads"
+    if full_argmax:
+        t0 = time.perf_counter()
+        xi = front()
+        allidx = np.arange(wl.J)
+        fm = _oracle_map(O, wl, xi, win, allidx, workers)
+        full = {"argmax": np.argmax(fm, axis=1), "seconds": time.perf_counter() - t0}
+        del fm
+    info = {"value": legs["all_cores"]["value"], "unit": "cand-pair evals/s", "cores": workers,
+            "kind": "oracle", "cpu_model": _cpu_model(), "host_cpu_count": os.cpu_count(),
+            "blas_threads_default": _blas_threads(), "single_thread": legs["single_thread"],
+            "all_cores": legs["all_cores"],
+            "sample": (f"all {wl.F} frames; a seeded sample of {idx.size} of {wl.J} candidates "
+                       f"on {workers} threads (candidate chunks, one BLAS thread each) and "
+                       f"{idx1.size} of them on one thread; spectra + PHAT + GCC samples + "
+                       f"Nyquist map + argmax in float64 NumPy; median of {reps} runs")}
+    if full is not None:
+        info["full_map_seconds_all_cores"] = full["seconds"]
+    elif "full_map_skipped" in legs:
+        info["full_map_skipped"] = legs["full_map_skipped"]
+    return info, idx, ref, (None if full is None else full["argmax"])
+
+
+def cpu_baseline_subset_parity(wl, idx, dtypes_maps, frames=None):
+    """Sampled parity of larger configurations: the oracle's Nyquist map at the
+    candidates idx (of `frames`, default all of the workload's) against each
+    GPU map's columns there."""
+    import oracle as O
+    K = O.n_bins(wl.L, wl.fs)
+    w = O.bin_weights(wl.L, K)
+    win = O.pair_windows(wl.mic_xyz, wl.c, wl.fs / 2, wl.n_aux)
+    fr = wl.frames if frames is None else frames
+    psi = O.phat_cross_spectra(O.spectra(fr, O.window(wl.L), K))
     xi = O.gcc_samples(psi, wl.fs, wl.L, w, win)
-    dt = O.tdoa(wl.mic_xyz, cand, wl.c)
-    ref = O.srp_nyquist(xi, dt, win)
-    O.peaks(ref)
-    sec = time.perf_counter() - t0
-    rate = wl.F * idx.size * wl.P / sec
-    info = {"value": rate, "unit": "cand-pair evals/s", "cores": int(blas_threads),
-            "kind": "oracle", "seconds": sec, "host_cpu_count": os.cpu_count(),
-            "sample": (f"all {wl.F} frames, {idx.size} of {wl.J} candidates (seeded random); "
-                       f"spectra + PHAT + GCC samples + Nyquist map + argmax in float64 NumPy; "
-                       f"elementwise steps single-threaded, matrix products on "
-                       f"{blas_threads} BLAS threads")}
-    return info, idx, ref
+    ref = _oracle_map(O, wl, xi, win, idx, min(16, os.cpu_count() or 1))
+    out = {}
+    for dt, sub in dtypes_maps.items():
+        e = np.sqrt(((sub - ref) ** 2).sum(1) / (ref ** 2).sum(1))
+        out[dt] = {"max_rel_err": float(e.max()), "median_rel_err": float(np.median(e))}
+    return out
 
 
 def serving_run(seconds: float, rate_per_array: float = 31.25, seed: int = 4,
@@ -287,6 +388,81 @@ def next_rows_leg(srp, torch, wl, g, frames, pipe, steps):
     return res
 
 
+def _timed(step, steps: int, n_marks: int):
+    """Run `step(events)` `steps` times after one untimed call; return the wall
+    ms per step and the mean ms between consecutive HIP-event marks."""
+    import torch
+    step(None)
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(n_marks)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    gaps = [float(np.mean([e[i].elapsed_time(e[i + 1]) for e in evs]))
+            for i in range(n_marks - 1)]
+    return ms, gaps
+
+
+def _dist_to_source(wl, idx):
+    """Median over frames of the distance (m) from the picked candidate to the
+    nearest true source."""
+    q = wl.candidates_at(np.asarray(idx))
+    d = np.linalg.norm(q[:, None, :] - wl.sources[None, :, :], axis=-1).min(axis=1)
+    return float(np.median(d))
+
+
+def other_geometry_leg(srp, torch, cfg: int, dtypes, steps: dict, F=None):
+    """Nyquist map on the 32-mic (4M candidates, L = 2048) or the 64-mic
+    (9M candidates, 48 kHz, L = 4096) geometry: per dtype, ms per step and the
+    map kernel's TFLOP/s against the matrix-core peak. Returns the result, the
+    workload, and a keep-map pipeline's maps for sampled parity."""
+    import workloads as WL
+    dev = torch.device("cuda:0")
+    wl = WL.make(cfg, F=F)
+    g = srp.Geometry(wl.mic_xyz, wl.candidates(), fs=wl.fs, L=wl.L, c=wl.c, n_aux=wl.n_aux)
+    pipe = srp.SrpPipeline(g, wl.F, device=dev, keep_map=False)
+    frames = torch.from_numpy(wl.frames).to(dev)
+    stream = torch.cuda.current_stream()
+    NP = g.W_total
+    flops = 2.0 * NP * wl.J * wl.F
+    res = {"workload": wl.name, "M": wl.M, "P": wl.P, "J": wl.J, "F": wl.F, "L": wl.L,
+           "K": g.K, "fs": wl.fs, "samples_per_frame_NP": NP}
+    peaks = {}
+    for dt in dtypes:
+        def step(ev, dt=dt):
+            psi = srp.cross_spectra(g, frames, out=pipe.psi, workspace=pipe.workspace)
+            xi = srp.gcc_samples(g, psi, out=pipe.samples_buffer(dt), dtype=dt)
+            if ev is not None:
+                ev[0].record(stream)
+            srp.map_nyquist(g, xi, dtype=dt, want_map=False, peaks_out=pipe.peaks)
+            if ev is not None:
+                ev[1].record(stream)
+        ms, (t_map,) = _timed(step, steps[dt], 2)
+        idx = srp.decode_peaks(pipe.peaks)[0].copy()
+        peaks[dt] = idx
+        ach = flops / (t_map * 1e-3) / 1e12
+        peak = PEAK_FP32_TFLOPS if dt == "fp32" else PEAK_BF16_TFLOPS
+        # weight pairs generated per second: one (candidate, pair) pair of sinc
+        # weights per 256-frame tile (BF16/FP16) or per 8-frame tile (FP32)
+        tile = 8 if dt == "fp32" else 256
+        wp = wl.J * wl.P * (-(-wl.F // tile))
+        res[dt] = {"steps": steps[dt], "ms_per_step": ms, "map_kernel_ms": t_map,
+                   "value": wl.F * wl.J * wl.P / (ms * 1e-3), "unit": "cand-pair evals/s",
+                   "achieved_tflops": ach, "peak_tflops": peak, "frac": ach / peak,
+                   "weight_pairs_per_s": wp / (t_map * 1e-3),
+                   "median_dist_to_source_m": _dist_to_source(wl, idx)}
+        print(f"[bench] {wl.name} nyquist {dt}: {ms:.1f} ms/step (map {t_map:.1f} ms, "
+              f"{ach:.0f} TFLOP/s)", file=sys.stderr, flush=True)
+    for a in dtypes:
+        for b in dtypes:
+            if a < b:
+                res[f"argmax_agree_{a}_{b}"] = float(np.mean(peaks[a] == peaks[b]))
+    del pipe
+    return res, wl, g, frames, peaks
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -296,13 +472,20 @@ def main():
     ap.add_argument("--conv-steps", type=int, default=3)
     ap.add_argument("--no-conventional", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-other-geometries", action="store_true",
+                    help="skip the 32-mic and 64-mic Nyquist legs")
     ap.add_argument("--next-rows", action="store_true",
                     help="also measure the band-limited map (f_max = fs/4) and the refined "
                          "peak search (kept out of the default run: the band-limited map "
                          "launches the same kernel instances as the timed one, which would "
                          "mix two workloads in a kernel trace of the default command)")
-    ap.add_argument("--cpu-candidates", type=int, default=120000,
-                    help="candidates of the oracle's timed sample (about 10 s on 16 threads)")
+    ap.add_argument("--cpu-candidates", type=int, default=60000,
+                    help="candidates of the oracle's all-core timed sample")
+    ap.add_argument("--cpu-candidates-single", type=int, default=4000,
+                    help="candidates of the oracle's single-thread timed sample")
+    ap.add_argument("--cpu-reps", type=int, default=3)
+    ap.add_argument("--no-full-oracle-argmax", action="store_true",
+                    help="skip the oracle's whole-map argmax of the timed workload")
     ap.add_argument("--serving-seconds", type=float, default=10.0,
                     help="length of the serving run (0 skips it)")
     ap.add_argument("--serving-leg", choices=("fp32", "bf16", "fp16"), default=None,
@@ -350,6 +533,7 @@ def main():
     pipe = srp.SrpPipeline(g, wl.F, device=dev, keep_map=False)
     frames = torch.from_numpy(wl.frames).to(dev)
     stream = torch.cuda.current_stream()
+    picks = {}   # per path: the per-frame argmax indices
 
     def nyquist_step(ev=None, dtype="fp32"):
         if ev is not None:
@@ -406,22 +590,20 @@ def main():
                       "samples_per_frame_NP": NP, "N_avg_samples_per_pair": NP / wl.P},
            "roofline": roofline,
            "kernels_ms": {"cross_spectra": t_spec, "gcc_samples": t_gcc, "map_nyquist": t_map},
-           "gcc_samples_tflops": flops_gcc / (t_gcc * 1e-3) / 1e12}
+           "gcc_samples_tflops": flops_gcc / (t_gcc * 1e-3) / 1e12,
+           "paper_complexity_no_hardware_stated": {
+               "C_conv_per_frame_JPK": wl.J * wl.P * g.K, "C_samp_per_frame_NPK": NP * g.K,
+               "C_int_per_frame_NPJ": NP * wl.J, "R_samp_N_over_J": NP / wl.P / wl.J,
+               "R_int_N_over_K": NP / wl.P / g.K}}
+    picks["nyquist_fp32"] = srp.decode_peaks(pipe.peaks)[0].copy()
+    ref_pk = picks["nyquist_fp32"]
 
     # low-precision Nyquist beside FP32 (same frames, same step structure)
-    ref_pk = srp.decode_peaks(pipe.peaks)[0].copy()
     for dt in ("bf16", "fp16"):
-        nyquist_step(dtype=dt)
-        torch.cuda.synchronize()
-        evl = [[torch.cuda.Event(enable_timing=True) for _ in range(4)]
-               for _ in range(args.steps)]
-        l0 = time.perf_counter()
-        for k in range(args.steps):
-            nyquist_step(evl[k], dtype=dt)
-        torch.cuda.synchronize()
-        ms_l = (time.perf_counter() - l0) * 1e3 / args.steps
-        t_map_l = float(np.mean([e[2].elapsed_time(e[3]) for e in evl]))
-        pk_l = srp.decode_peaks(pipe.peaks)[0]
+        ms_l, (_, _, t_map_l) = _timed(lambda ev, dt=dt: nyquist_step(ev, dtype=dt),
+                                       args.steps, 4)
+        pk_l = srp.decode_peaks(pipe.peaks)[0].copy()
+        picks[f"nyquist_{dt}"] = pk_l
         ach = flops_map / (t_map_l * 1e-3) / 1e12
         out[f"nyquist_{dt}"] = {
             "value": evals / (ms_l * 1e-3), "unit": "cand-pair evals/s", "ms_per_step": ms_l,
@@ -454,17 +636,9 @@ def main():
             if ev is not None:
                 ev[2].record(stream)
 
-        cached_step()
-        torch.cuda.synchronize()
-        evc = [[torch.cuda.Event(enable_timing=True) for _ in range(3)]
-               for _ in range(args.steps)]
-        q0 = time.perf_counter()
-        for k in range(args.steps):
-            cached_step(evc[k])
-        torch.cuda.synchronize()
-        ms_c = (time.perf_counter() - q0) * 1e3 / args.steps
-        t_map_c = float(np.mean([e[1].elapsed_time(e[2]) for e in evc]))
-        pk_c = srp.decode_peaks(pipe.peaks)[0]
+        ms_c, (_, t_map_c) = _timed(cached_step, args.steps, 3)
+        pk_c = srp.decode_peaks(pipe.peaks)[0].copy()
+        picks["nyquist_bf16_cached"] = pk_c
         ach = flops_map / (t_map_c * 1e-3) / 1e12
         out["nyquist_bf16_cached"] = {
             "value": evals / (ms_c * 1e-3), "unit": "cand-pair evals/s", "ms_per_step": ms_c,
@@ -492,43 +666,114 @@ def main():
               file=sys.stderr, flush=True)
 
     if not args.no_conventional:
-        def conv_step():
-            psi = srp.cross_spectra(g, frames, out=pipe.psi, workspace=pipe.workspace)
-            srp.map_conventional(g, psi, want_map=False, peaks_out=pipe.peaks)
-        conv_step()
-        torch.cuda.synchronize()
-        c0 = time.perf_counter()
-        for _ in range(args.conv_steps):
-            conv_step()
-        torch.cuda.synchronize()
-        ms_conv = (time.perf_counter() - c0) * 1e3 / args.conv_steps
-        flops_conv = 4.0 * g.K * wl.P * wl.J * wl.F   # J P K complex MACs, real part (Eq. SRPomp)
-        out["conventional"] = {"value": evals / (ms_conv * 1e-3), "unit": "cand-pair evals/s",
-                               "ms_per_step": ms_conv, "steps": args.conv_steps,
-                               "algorithmic_tflops": flops_conv / (ms_conv * 1e-3) / 1e12,
-                               "nyquist_speedup": ms_conv / ms_step,
-                               "argmax_agree_with_nyquist_fp32":
-                                   float(np.mean(srp.decode_peaks(pipe.peaks)[0] == ref_pk))}
-        print(f"[bench] conventional fp32: {ms_conv:.1f} ms/step", file=sys.stderr, flush=True)
+        # conventional SRP (Eq. SRPomp) on the same frames: FP32 from the
+        # complex spectra; BF16/FP16 from the weighted spectra rounded once
+        flops_conv = 4.0 * g.K * wl.P * wl.J * wl.F   # J P K complex MACs, real part
+        for dt in ("fp32", "bf16", "fp16"):
+            low = dt != "fp32"
+            spec = srp.spectra_lowp_buffer(g, wl.F, dt, dev) if low else None
+
+            def conv_step(ev, dt=dt, low=low, spec=spec):
+                psi = srp.cross_spectra(g, frames, out=pipe.psi, workspace=pipe.workspace)
+                if low:
+                    psi = srp.spectra_lowp(g, psi, dt, out=spec)
+                if ev is not None:
+                    ev[0].record(stream)
+                srp.map_conventional(g, psi, dtype=dt, want_map=False, peaks_out=pipe.peaks)
+                if ev is not None:
+                    ev[1].record(stream)
+            ms_conv, (t_cmap,) = _timed(conv_step, args.conv_steps, 2)
+            pk = srp.decode_peaks(pipe.peaks)[0].copy()
+            key = "conventional" if dt == "fp32" else f"conventional_{dt}"
+            picks[key] = pk
+            ach = flops_conv / (t_cmap * 1e-3) / 1e12
+            peak = PEAK_FP32_TFLOPS if dt == "fp32" else PEAK_BF16_TFLOPS
+            nyq = "nyquist_fp32" if dt == "fp32" else f"nyquist_{dt}"
+            ms_nyq = ms_step if dt == "fp32" else out[nyq]["ms_per_step"]
+            out[key] = {"value": evals / (ms_conv * 1e-3), "unit": "cand-pair evals/s",
+                        "ms_per_step": ms_conv, "map_kernel_ms": t_cmap,
+                        "steps": args.conv_steps, "algorithmic_tflops": ach,
+                        "peak_tflops": peak, "frac": ach / peak,
+                        "nyquist_speedup": ms_conv / ms_nyq,
+                        "argmax_agree_with_nyquist_same_dtype": float(np.mean(pk == picks[nyq]))}
+            del spec
+            print(f"[bench] conventional {dt}: {ms_conv:.1f} ms/step (map {t_cmap:.1f} ms, "
+                  f"{ach:.0f} TFLOP/s)", file=sys.stderr, flush=True)
+        out["conventional_vs_nyquist_argmax"] = {
+            dt: float(np.mean(picks["conventional" if dt == "fp32" else f"conventional_{dt}"]
+                              == picks["conventional"]))
+            for dt in ("fp32", "bf16", "fp16")}
+
+    # localisation accuracy of every path: median distance from the pick to the
+    # nearest true source (the same frames, the same sources)
+    out["median_dist_to_source_m"] = {k: _dist_to_source(wl, v) for k, v in picks.items()}
+
+    others = {}
+    if not args.no_other_geometries:
+        del pipe
+        torch.cuda.empty_cache()
+        r3, wl3, g3, fr3, pk3 = other_geometry_leg(
+            srp, torch, 3, ("fp32", "bf16", "fp16"), {"fp32": 2, "bf16": 3, "fp16": 3})
+        out["precision_32mic"] = r3
+        others[3] = (wl3, g3, fr3, pk3)
+        r5, wl5, g5, fr5, pk5 = other_geometry_leg(
+            srp, torch, 5, ("bf16", "fp16"), {"bf16": 2, "fp16": 2})
+        out["largest_64mic"] = r5
+        others[5] = (wl5, g5, fr5, pk5)
+        pipe = None
 
     if not args.no_cpu_baseline:
-        cb, idx, ref = cpu_baseline(wl, args.cpu_candidates)
+        cb, idx, ref, full_arg = cpu_baseline(wl, args.cpu_candidates, args.cpu_candidates_single,
+                                              reps=args.cpu_reps,
+                                              full_argmax=not args.no_full_oracle_argmax)
+        gpu_rate = {"nyquist_fp32": value, "nyquist_bf16": out["nyquist_bf16"]["value"]}
+        cb["gpu_over_oracle"] = {k: {"all_cores": v / cb["all_cores"]["value"],
+                                     "single_thread": v / cb["single_thread"]["value"]}
+                                 for k, v in gpu_rate.items()}
         out["cpu_baseline"] = cb
+        if full_arg is not None:
+            out["argmax_vs_oracle_full_map"] = {k: float(np.mean(v == full_arg))
+                                                for k, v in picks.items()}
+            out["median_dist_to_source_m"]["oracle_nyquist_fp64"] = _dist_to_source(wl, full_arg)
         # parity of the timed configuration on the sampled candidates (not timed)
-        del pipe
         keep = srp.SrpPipeline(g, wl.F, device=dev, keep_map=True)
         sel = torch.from_numpy(idx).to(dev)
-        out["parity_sampled"] = {"candidates": int(idx.size)}
+        maps = {}
         for dt in ("fp32", "bf16", "fp16"):
             m, _ = keep.nyquist(frames, dtype=dt)
-            sub = m[:, sel].cpu().numpy().astype(np.float64)
-            e = np.sqrt(((sub - ref) ** 2).sum(1) / (ref ** 2).sum(1))
-            out["parity_sampled"][dt] = {"max_rel_err": float(e.max()),
-                                         "median_rel_err": float(np.median(e))}
-        err = np.asarray([out["parity_sampled"]["fp32"]["max_rel_err"]])
-        print(f"[bench] cpu baseline {cb['value']:.3e} evals/s on {cb['cores']} BLAS threads "
-              f"({cb['seconds']:.1f}s); sampled map rel err max {err.max():.2e}",
+            maps[dt] = m[:, sel].cpu().numpy().astype(np.float64)
+        del keep
+        e = {}
+        for dt, sub in maps.items():
+            r = np.sqrt(((sub - ref) ** 2).sum(1) / (ref ** 2).sum(1))
+            e[dt] = {"max_rel_err": float(r.max()), "median_rel_err": float(np.median(r))}
+        out["parity_sampled"] = {"candidates": int(idx.size), **e}
+        print(f"[bench] cpu baseline {cb['value']:.3e} evals/s on {cb['cores']} threads, "
+              f"{cb['single_thread']['value']:.3e} on one; sampled map rel err max "
+              f"{e['fp32']['max_rel_err']:.2e} (fp32) {e['bf16']['max_rel_err']:.2e} (bf16)",
               file=sys.stderr, flush=True)
+        # sampled parity of the other geometries: a seeded candidate sample and
+        # the first frames (the oracle's GCC samples of all frames would take minutes)
+        for cfg, key, n_c, n_f in ((3, "precision_32mic", 1000, 8), (5, "largest_64mic", 200, 2)):
+            if cfg not in others:
+                continue
+            wlx, gx, frx, _ = others[cfg]
+            rng = np.random.default_rng(cfg)
+            idx_x = np.sort(rng.choice(wlx.J, size=n_c, replace=False))
+            kp = srp.SrpPipeline(gx, n_f, device=dev, keep_map=True)
+            selx = torch.from_numpy(idx_x).to(dev)
+            subs = {}
+            for dt in out[key]:
+                if dt in ("fp32", "bf16", "fp16"):
+                    m, _ = kp.nyquist(frx[:n_f], dtype=dt)
+                    subs[dt] = m[:, selx].cpu().numpy().astype(np.float64)
+            del kp
+            out[key]["parity_sampled"] = {
+                "candidates": n_c, "frames": n_f,
+                **cpu_baseline_subset_parity(wlx, idx_x, subs, frames=wlx.frames[:n_f])}
+            print(f"[bench] {key} sampled parity: " + ", ".join(
+                f"{dt} {v['max_rel_err']:.2e}" for dt, v in out[key]["parity_sampled"].items()
+                if isinstance(v, dict)), file=sys.stderr, flush=True)
 
     if args.serving_seconds > 0:
         # the offered load (31.25 frames/s per array, 2,007 frames/s in all) in

@@ -10,7 +10,7 @@ from ._lib import (DTYPES, EXPORTS, Geometry, SrpError, argmax, cross_spectra, d
                    SRP_ERR_UNSUPPORTED, conventional_supports, cross_spectra_noalloc,
                    batched_workspace_bytes, gcc_samples, lib, map_conventional, map_nyquist,
                    map_nyquist_batched, map_nyquist_cached, map_nyquist_points, nyquist_weights,
-                   spectra_lowp,
+                   spectra_lowp, spectra_lowp_buffer,
                    nyquist_weights_bytes, pair_layout, sample_torch_dtype, unpack_samples,
                    version)
 from .pipeline import SrpPipeline  # noqa: F401
