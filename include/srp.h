@@ -127,7 +127,9 @@ srp_status srp_geometry_query(const srp_geometry_t* g, srp_geometry_info* info, 
 /* Frees the handle's device memory. The caller synchronises first. NULL is a no-op. */
 void srp_geometry_destroy(srp_geometry_t* g);
 
-/* Bytes of device workspace srp_cross_spectra needs for F frames (F * M * K * 8). */
+/* Bytes of device workspace srp_cross_spectra and srp_gcc_samples_frames need
+ * for F frames: F * M * Kr * 8, Kr = K rounded up to a multiple of 16 (the
+ * per-microphone unit phasors, one row of Kr bins per frame and microphone). */
 srp_status srp_cross_spectra_workspace(const srp_geometry_t* g, int32_t F, size_t* bytes);
 
 /* Frequency-domain GCC of every pair (Eq. corrmatrix with the PHAT weight):
@@ -148,8 +150,9 @@ srp_status srp_cross_spectra(const srp_geometry_t* g, const float* frames, int32
  * static device array of 64 MiB per GPU, present from the library's load
  * until the process ends, its address looked up once per device at the first
  * call there. Same arguments, result and errors as srp_cross_spectra, except:
- *   F * M * K * 8 bytes must not exceed 64 MiB, else SRP_ERR_INVALID_ARG with
- *   nothing enqueued (e.g. F <= 1022 for 16 mics and K = 513).
+ *   F * M * Kr * 8 bytes (Kr = K rounded up to a multiple of 16) must not
+ *   exceed 64 MiB, else SRP_ERR_INVALID_ARG with nothing enqueued (e.g.
+ *   F <= 992 for 16 mics and K = 513, Kr = 528).
  * Every call on a GPU shares that GPU's buffer: calls that overlap on one GPU
  * (several streams or threads at once) race and must be serialised by the
  * caller. The call itself allocates nothing. */
@@ -165,6 +168,23 @@ srp_status srp_cross_spectra_noalloc(const srp_geometry_t* g, const float* frame
  *   xi     device, F x S elements of that type, written */
 srp_status srp_gcc_samples(const srp_geometry_t* g, const float* psi, int32_t F, int32_t dtype,
                            void* xi, void* stream);
+
+/* Frames to GCC samples in one call (Section 2.1, Eq. corrmatrix with the PHAT
+ * weight, then Section 3.2, first step): the same samples as srp_cross_spectra
+ * followed by srp_gcc_samples, with psi_p(k) = ytil_m(k) ytil_m'(k)^* formed
+ * on chip from the per-microphone unit phasors ytil = y / |y| instead of being
+ * written to memory (F P K complex values fewer in memory traffic each way).
+ *   frames     device, F x M x L float32
+ *   weighting  SRP_PHAT
+ *   dtype      storage type of xi: SRP_FP32, SRP_BF16 or SRP_FP16 (float32
+ *              accumulation, rounded once)
+ *   workspace  device, >= srp_cross_spectra_workspace bytes (overwritten)
+ *   xi         device, F x S elements of that type, written (layout above)
+ * F >= 1. The samples equal those of the two-call path up to float32 rounding
+ * (the sums run in another order). */
+srp_status srp_gcc_samples_frames(const srp_geometry_t* g, const float* frames, int32_t F,
+                                  int32_t weighting, int32_t dtype, void* workspace,
+                                  size_t workspace_bytes, void* xi, void* stream);
 
 /* Input of the BF16/FP16 conventional map: the cross-spectra weighted by the
  * bin weights (Eq. SRP_T) and rounded once to the 16-bit type,

@@ -39,7 +39,8 @@ PHAT = 0
 # exported symbols of include/srp.h
 EXPORTS = ("srp_pair_layout", "srp_geometry", "srp_geometry_query", "srp_geometry_destroy",
            "srp_cross_spectra_workspace", "srp_cross_spectra", "srp_cross_spectra_noalloc",
-           "srp_gcc_samples", "srp_spectra_lowp_bytes", "srp_spectra_lowp",
+           "srp_gcc_samples", "srp_gcc_samples_frames", "srp_spectra_lowp_bytes",
+           "srp_spectra_lowp",
            "srp_map_conventional", "srp_map_nyquist", "srp_map_nyquist_batched_workspace",
            "srp_map_nyquist_batched", "srp_nyquist_weights_bytes", "srp_nyquist_weights",
            "srp_map_nyquist_cached", "srp_map_nyquist_points", "srp_argmax", "srp_last_error",
@@ -93,6 +94,7 @@ def lib() -> C.CDLL:
     L.srp_cross_spectra.argtypes = [vp, vp, i32, i32, vp, C.c_size_t, vp, vp]
     L.srp_cross_spectra_noalloc.argtypes = [vp, vp, i32, i32, vp, vp]
     L.srp_gcc_samples.argtypes = [vp, vp, i32, i32, vp, vp]
+    L.srp_gcc_samples_frames.argtypes = [vp, vp, i32, i32, i32, vp, C.c_size_t, vp, vp]
     L.srp_spectra_lowp_bytes.argtypes = [vp, i32, i32, C.POINTER(C.c_size_t)]
     L.srp_spectra_lowp.argtypes = [vp, vp, i32, i32, vp, C.c_size_t, vp]
     L.srp_map_conventional.argtypes = [vp, vp, i32, i32, vp, vp, vp]
@@ -256,6 +258,29 @@ def gcc_samples(g: Geometry, psi, out=None, dtype: str = "fp32", stream=None):
     _need_cuda(out, "xi", tdt, (F, g.S))
     _check(lib().srp_gcc_samples(g.handle, psi.data_ptr(), F, DTYPES[dtype if dtype != "fp64" else "fp32"],
                                  out.data_ptr(), _stream_handle(stream)))
+    return out
+
+
+def gcc_samples_frames(g: Geometry, frames, out=None, dtype: str = "fp32", workspace=None,
+                       stream=None):
+    """frames [F][M][L] float32 -> xi [F][S] in one call (srp_gcc_samples_frames):
+    the cross-spectra are formed on chip from the per-microphone phasors."""
+    import torch
+    _need_cuda(frames, "frames", torch.float32)
+    F = frames.shape[0]
+    if frames.dim() != 3 or frames.shape[1] != g.M or frames.shape[2] != g.L:
+        raise ValueError(f"frames must be [F][{g.M}][{g.L}]")
+    if workspace is None:
+        workspace = torch.empty(g.workspace_bytes(F), dtype=torch.uint8, device=frames.device)
+    tdt = sample_torch_dtype(dtype)
+    if out is None:
+        out = torch.empty((F, g.S), dtype=tdt, device=frames.device)
+    _need_cuda(out, "xi", tdt, (F, g.S))
+    _check(lib().srp_gcc_samples_frames(g.handle, frames.data_ptr(), F, PHAT,
+                                        DTYPES[dtype if dtype != "fp64" else "fp32"],
+                                        workspace.data_ptr(),
+                                        workspace.numel() * workspace.element_size(),
+                                        out.data_ptr(), _stream_handle(stream)))
     return out
 
 

@@ -4,6 +4,7 @@
 // are reproducible bit for bit.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdint>
@@ -100,6 +101,7 @@ void free_geometry(srp_geometry_s* g) {
   hipFree(g->d_cand);
   hipFree(g->d_pairs);
   hipFree(g->d_gcc_tiles);
+  hipFree(g->d_gcc_items);
   hipFree(g->d_nyq_runs);
   hipFree(g->d_nyq_recs);
   hipFree(g->d_convmx_recs);
@@ -107,6 +109,7 @@ void free_geometry(srp_geometry_s* g) {
   hipFree(g->d_window);
   hipFree(g->d_twiddle);
   hipFree(g->d_gcc_table);
+  hipFree(g->d_gcc_wtable);
   hipFree(g->d_binw);
   hipFree(g->d_zero);
   hipFree(g->d_chunk_pair);
@@ -212,6 +215,16 @@ srp_status srp_geometry(const double* mic_xyz, int32_t M, const double* cand_xyz
     const int W = 2 * g->pairs[p].h + 1;
     for (int t0 = 0; t0 < W; t0 += kGccLagTile)
       g->gcc_tiles.push_back(LagRun{p, t0, W - t0 < kGccLagTile ? W - t0 : kGccLagTile, 0});
+    // the fused GCC kernel: the window's ceil(W / 32) tiles (whose last one also
+    // covers the layout's gap up to the next multiple of 8) in about equal
+    // items of at most kGccItemTiles tiles
+    {
+      const int ntiles = (W + kGccLagTile - 1) / kGccLagTile;
+      const int n_it = (ntiles + kGccItemTiles - 1) / kGccItemTiles;
+      const int per_it = (ntiles + n_it - 1) / n_it;
+      for (int t = 0; t < ntiles; t += per_it)
+        g->gcc_items.push_back(GccItem{p, t, ntiles - t < per_it ? ntiles - t : per_it, 0});
+    }
     // a window longer than one run is split into runs of about equal length
     // (all but the last a multiple of kSampleAlign lags, so every run starts
     // on an aligned column), not into full runs and a short remainder: each
@@ -228,12 +241,19 @@ srp_status srp_geometry(const double* mic_xyz, int32_t M, const double* cand_xyz
   // pair (no lags, no copy, no pair change)
   while (g->nyq_runs.size() % 6)
     g->nyq_runs.push_back(LagRun{P - 1, 2 * (np[P - 1] + n_aux) + 1, 0, 0});
+  // the fused GCC kernel deals its units out largest first
+  std::stable_sort(g->gcc_items.begin(), g->gcc_items.end(),
+                   [](const GccItem& a, const GccItem& b) { return a.nt > b.nt; });
   for (int p = 0; p < P; ++p)
     for (int k0 = 0; k0 < in.K; k0 += kConvRunBins)
       g->conv_runs.push_back(LagRun{p, k0, in.K - k0 < kConvRunBins ? in.K - k0 : kConvRunBins, 0});
   if (g->conv_runs.size() % 2) g->conv_runs.push_back(LagRun{P - 1, in.K, 0, 0});
   const int K = in.K;
-  g->gcc_nw = 2 * h_max + 1 + kGccLagTile;
+  g->Kr = (K + 15) / 16 * 16;
+  const int Kr = g->Kr;
+  // lags -h_max .. h_max plus a tile's overhang and one more, rounded to even
+  // (16-byte aligned copies of lag pairs in the fused GCC kernel)
+  g->gcc_nw = 2 * h_max + 2 + kGccLagTile;
 
   // float64 tables, each rounded once to float32
   std::vector<float> win(L);
@@ -243,17 +263,18 @@ srp_status srp_geometry(const double* mic_xyz, int32_t M, const double* cand_xyz
                                 : window == SRP_WIN_SQRT_HANN ? std::sqrt(hann)
                                                               : 1.0);
   }
-  std::vector<float2> tw(L / 2);
-  for (int t = 0; t < L / 2; ++t) {
+  std::vector<float2> tw(L);
+  for (int t = 0; t < L; ++t) {
     const double a = 2.0 * M_PI * t / L;
     tw[t] = make_float2(static_cast<float>(std::cos(a)), static_cast<float>(-std::sin(a)));
   }
-  std::vector<float> binw(K, 2.0f);
+  std::vector<float> binw(Kr, 0.0f);
+  for (int k = 0; k < K; ++k) binw[k] = 2.0f;
   binw[0] = 1.0f;
   if (2 * (K - 1) == L) binw[K - 1] = 1.0f;
   // GCC phase 2 pi f_k n T in turns: k n fs T / L, reduced mod 1 exactly when
   // fs T = 1/2 ... in general through the float64 fraction.
-  std::vector<float2> gtab((size_t)K * g->gcc_nw);
+  std::vector<float2> gtab((size_t)Kr * g->gcc_nw, make_float2(0.0f, 0.0f));
   const bool integer_lags = (2.0 * f_max == fs);
   for (int k = 0; k < K; ++k) {
     for (int j = 0; j < g->gcc_nw; ++j) {
@@ -292,6 +313,7 @@ srp_status srp_geometry(const double* mic_xyz, int32_t M, const double* cand_xyz
   if (e == hipSuccess) e = upload(&g->d_cand, cand_soa.data(), cand_soa.size(), s);
   if (e == hipSuccess) e = upload(&g->d_pairs, g->pairs.data(), g->pairs.size(), s);
   if (e == hipSuccess) e = upload(&g->d_gcc_tiles, g->gcc_tiles.data(), g->gcc_tiles.size(), s);
+  if (e == hipSuccess) e = upload(&g->d_gcc_items, g->gcc_items.data(), g->gcc_items.size(), s);
   if (e == hipSuccess) e = upload(&g->d_nyq_runs, g->nyq_runs.data(), g->nyq_runs.size(), s);
   std::vector<RunRec> recs(g->nyq_runs.size());
   for (size_t i = 0; i < recs.size(); ++i) {
@@ -346,6 +368,13 @@ srp_status srp_geometry(const double* mic_xyz, int32_t M, const double* cand_xyz
   if (e == hipSuccess) e = upload(&g->d_window, win.data(), win.size(), s);
   if (e == hipSuccess) e = upload(&g->d_twiddle, tw.data(), tw.size(), s);
   if (e == hipSuccess) e = upload(&g->d_gcc_table, gtab.data(), gtab.size(), s);
+  // the fused GCC kernel's table: w_k (1 or 2, so exact) times the phase table
+  for (int k = 0; k < K; ++k)
+    for (int j = 0; j < g->gcc_nw; ++j) {
+      float2& v = gtab[(size_t)k * g->gcc_nw + j];
+      v = make_float2(binw[k] * v.x, binw[k] * v.y);
+    }
+  if (e == hipSuccess) e = upload(&g->d_gcc_wtable, gtab.data(), gtab.size(), s);
   if (e == hipSuccess) e = upload(&g->d_binw, binw.data(), binw.size(), s);
   const std::vector<float> zeros(64, 0.0f);
   if (e == hipSuccess) e = upload(&g->d_zero, zeros.data(), zeros.size(), s);
@@ -387,7 +416,7 @@ void srp_geometry_destroy(srp_geometry_t* g) {
 srp_status srp_cross_spectra_workspace(const srp_geometry_t* g, int32_t F, size_t* bytes) {
   if (g == nullptr || bytes == nullptr) return fail(SRP_ERR_INVALID_ARG, "NULL argument");
   if (F < 1) return fail(SRP_ERR_INVALID_ARG, "F must be >= 1");
-  *bytes = (size_t)F * g->info.M * g->info.K * sizeof(float2);
+  *bytes = (size_t)F * g->info.M * g->Kr * sizeof(float2);
   return SRP_OK;
 }
 
@@ -398,7 +427,7 @@ srp_status srp_cross_spectra(const srp_geometry_t* g, const float* frames, int32
     return fail(SRP_ERR_INVALID_ARG, "srp_cross_spectra: NULL argument");
   if (F < 1) return fail(SRP_ERR_INVALID_ARG, "F must be >= 1");
   if (weighting != SRP_PHAT) return fail(SRP_ERR_UNSUPPORTED, "only PHAT weighting");
-  const size_t need = (size_t)F * g->info.M * g->info.K * sizeof(float2);
+  const size_t need = (size_t)F * g->info.M * g->Kr * sizeof(float2);
   if (workspace_bytes < need) return fail(SRP_ERR_INVALID_ARG, "workspace too small");
   DeviceGuard dg(g->device);
   if (!dg.ok) return fail(SRP_ERR_DEVICE, "cannot select the geometry's device");
@@ -417,10 +446,11 @@ srp_status srp_cross_spectra_noalloc(const srp_geometry_t* g, const float* frame
     return fail(SRP_ERR_INVALID_ARG, "srp_cross_spectra_noalloc: NULL argument");
   if (F < 1) return fail(SRP_ERR_INVALID_ARG, "F must be >= 1");
   if (weighting != SRP_PHAT) return fail(SRP_ERR_UNSUPPORTED, "only PHAT weighting");
-  const size_t need = (size_t)F * g->info.M * g->info.K;
+  const size_t need = (size_t)F * g->info.M * g->Kr;
   if (need > kCrossStaticElems)
     return fail(SRP_ERR_INVALID_ARG,
-                "srp_cross_spectra_noalloc: F * M * K * 8 bytes exceed the 64 MiB static buffer");
+                "srp_cross_spectra_noalloc: F * M * Kr * 8 bytes exceed the 64 MiB static buffer "
+                "(Kr = K rounded up to a multiple of 16)");
   DeviceGuard dg(g->device);
   if (!dg.ok) return fail(SRP_ERR_DEVICE, "cannot select the geometry's device");
   float2* ytil = nullptr;
@@ -446,6 +476,28 @@ srp_status srp_gcc_samples(const srp_geometry_t* g, const float* psi, int32_t F,
   hipError_t e = launch_gcc_samples(g, reinterpret_cast<const float2*>(psi), F, dtype, xi,
                                     static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return device_fail(e, "gcc_samples");
+  return SRP_OK;
+}
+
+srp_status srp_gcc_samples_frames(const srp_geometry_t* g, const float* frames, int32_t F,
+                                  int32_t weighting, int32_t dtype, void* workspace,
+                                  size_t workspace_bytes, void* xi, void* stream) {
+  if (g == nullptr || frames == nullptr || workspace == nullptr || xi == nullptr)
+    return fail(SRP_ERR_INVALID_ARG, "srp_gcc_samples_frames: NULL argument");
+  if (F < 1) return fail(SRP_ERR_INVALID_ARG, "F must be >= 1");
+  if (weighting != SRP_PHAT) return fail(SRP_ERR_UNSUPPORTED, "only PHAT weighting");
+  if (dtype != SRP_FP32 && dtype != SRP_BF16 && dtype != SRP_FP16)
+    return fail(SRP_ERR_UNSUPPORTED, "srp_gcc_samples_frames stores FP32, BF16 or FP16");
+  const size_t need = (size_t)F * g->info.M * g->Kr * sizeof(float2);
+  if (workspace_bytes < need) return fail(SRP_ERR_INVALID_ARG, "workspace too small");
+  DeviceGuard dg(g->device);
+  if (!dg.ok) return fail(SRP_ERR_DEVICE, "cannot select the geometry's device");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  float2* ytil = static_cast<float2*>(workspace);
+  hipError_t e = launch_fft_phat(g, frames, F, ytil, s);
+  if (e != hipSuccess) return device_fail(e, "fft_phat");
+  e = launch_gcc_phasor(g, ytil, F, dtype, xi, s);
+  if (e != hipSuccess) return device_fail(e, "gcc_phasor");
   return SRP_OK;
 }
 

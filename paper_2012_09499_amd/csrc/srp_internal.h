@@ -44,6 +44,14 @@ constexpr int kSampleAlign = 8;
 constexpr int kConvRunBins = 32;
 // Lag tiles of the GCC-sample kernel are 32 lags wide (one matrix-core tile).
 constexpr int kGccLagTile = 32;
+// Lag tiles per work unit of the fused GCC kernel (srp_gcc_samples_frames).
+constexpr int kGccItemTiles = 3;
+
+// Lag tiles [t0, t0 + nt) (32 lags each, counted from the window's first lag)
+// of pair p: the lags of one work unit of the fused GCC kernel.
+struct GccItem {
+  int32_t p, t0, nt, pad;
+};
 
 // Frames per array in one batched launch (srp_map_nyquist_batched): FP32
 // samples (vector units) and BF16/FP16 samples (16-frame matrix-core tile).
@@ -78,15 +86,17 @@ struct srp_geometry_s {
   int wg_per_cu[3] = {1, 1, 1};  // resident Nyquist workgroups per CU: FP32, BF16, FP16
   int wg_per_cu_conv[2] = {1, 1};  // resident BF16/FP16 conventional workgroups per CU
   int Kp = 0;              // bins of a row of the BF16/FP16 conventional input (K up to a multiple of 8)
+  int Kr = 0;              // bins of a row of the per-microphone phasors (K up to a multiple of 16)
   int n_convmx_runs = 0;   // 32-bin runs of the BF16/FP16 conventional map (even count)
   double inv_cT = 0.0;     // converts a path difference in metres into x = dt / T
   double fs_over_c = 0.0;  // converts a path difference in metres into samples
   int log2L = 0;
-  int gcc_nw = 0;          // row width of the GCC phase table (2 h_max + 1 + 32)
+  int gcc_nw = 0;          // row width of the GCC phase tables (2 h_max + 34, even)
   std::vector<srp::PairDesc> pairs;
   std::vector<int32_t> N_p;
   std::vector<int64_t> offsets;
   std::vector<srp::LagRun> gcc_tiles;  // lag tiles of srp_gcc_samples
+  std::vector<srp::GccItem> gcc_items;  // workgroup items of srp_gcc_samples_frames
   std::vector<srp::LagRun> nyq_runs;   // lag runs of srp_map_nyquist (even count)
   std::vector<srp::LagRun> conv_runs;  // bin runs (p, k0, len) of srp_map_conventional (even count)
   // device copies
@@ -94,14 +104,16 @@ struct srp_geometry_s {
   double* d_cand = nullptr;            // [3][J] (structure of arrays)
   srp::PairDesc* d_pairs = nullptr;    // [P]
   srp::LagRun* d_gcc_tiles = nullptr;
+  srp::GccItem* d_gcc_items = nullptr;
   srp::LagRun* d_nyq_runs = nullptr;
   srp::RunRec* d_nyq_recs = nullptr;   // one record per entry of nyq_runs
   srp::RunRec* d_convmx_recs = nullptr;  // 32-bin runs of the BF16/FP16 conventional map
   srp::LagRun* d_conv_runs = nullptr;
   float* d_window = nullptr;           // [L]
-  float2* d_twiddle = nullptr;         // [L/2] exp(-j 2 pi t / L)
-  float2* d_gcc_table = nullptr;       // [K][gcc_nw] (cos, -sin) of 2 pi f_k n T
-  float* d_binw = nullptr;             // [K]
+  float2* d_twiddle = nullptr;         // [L] exp(-j 2 pi t / L)
+  float2* d_gcc_table = nullptr;       // [Kr][gcc_nw] (cos, -sin) of 2 pi f_k n T (zeros past K)
+  float2* d_gcc_wtable = nullptr;      // [Kr][gcc_nw] the same times the bin weight w_k
+  float* d_binw = nullptr;             // [Kr] (zeros past K)
   float* d_zero = nullptr;             // 64 zeros (source of zero-filled staging chunks)
   int* d_chunk_pair = nullptr;         // pair of each 8-column chunk of the cached weights (-1: none)
 };
@@ -112,8 +124,12 @@ void set_error(const std::string& msg);
 
 // Kernel launchers. Each returns hipSuccess or the launch error; the host API
 // validates every argument before calling them.
+// ytil: [F][M][Kr] unit phasors (zeros past K).
 hipError_t launch_fft_phat(const srp_geometry_s* g, const float* frames, int F, float2* ytil,
                            hipStream_t s);
+// GCC samples of every pair from the phasors ytil (fused cross-spectrum + GCC).
+hipError_t launch_gcc_phasor(const srp_geometry_s* g, const float2* ytil, int F, int dtype,
+                             void* xi, hipStream_t s);
 hipError_t launch_cross(const srp_geometry_s* g, const float2* ytil, int F, float2* psi,
                         hipStream_t s);
 // Per-microphone phasor staging owned by the library (srp_cross_spectra_noalloc):

@@ -1,6 +1,7 @@
 """Frame-batch pipeline over the C ABI with preallocated device buffers.
 
-Nyquist path: srp_cross_spectra -> srp_gcc_samples -> srp_map_nyquist.
+Nyquist path: srp_gcc_samples_frames (FFT, PHAT phasors and GCC samples,
+the cross-spectra formed on chip) -> srp_map_nyquist.
 Conventional path: srp_cross_spectra -> srp_map_conventional (BF16/FP16:
 srp_cross_spectra -> srp_spectra_lowp -> srp_map_conventional).
 Every step is a libsrp kernel; buffers are torch tensors allocated once.
@@ -47,8 +48,8 @@ class SrpPipeline:
         this geometry and dtype) the map reads the cached weights instead of
         forming them."""
         F = frames.shape[0]
-        psi = self.spectra(frames)
-        xi = S.gcc_samples(self.g, psi, out=self.samples_buffer(dtype)[:F], dtype=dtype)
+        xi = S.gcc_samples_frames(self.g, frames, out=self.samples_buffer(dtype)[:F],
+                                  dtype=dtype, workspace=self.workspace)
         if weights is not None:
             return S.map_nyquist_cached(self.g, weights, xi, dtype=dtype,
                                         want_map=self.map is not None,

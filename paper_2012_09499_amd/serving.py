@@ -9,9 +9,9 @@ candidate grids) arrive as requests. The server
   close;
 * runs a loop that, whenever one of its batch slots is free, takes every
   pending frame (up to 8 per array in FP32, 16 in BF16/FP16) into a batch: one
-  host-to-device copy of the frames, per-array srp_cross_spectra and
-  srp_gcc_samples, then one ragged srp_map_nyquist_batched launch for all
-  arrays of the batch;
+  host-to-device copy of the frames, per-array srp_gcc_samples_frames (FFT,
+  PHAT phasors and GCC samples; the cross-spectra are formed on chip), then
+  one ragged srp_map_nyquist_batched launch for all arrays of the batch;
 * computes in FP32 (vector units) or BF16/FP16 (matrix cores, samples stored
   in that type, float32 accumulation), chosen per server;
 * keeps two batch slots on two HIP streams, so a batch is assembled and its
@@ -24,8 +24,12 @@ candidate grids) arrive as requests. The server
   requests of that batch;
 * records per-frame latency from arrival to observed completion.
 
-Results do not depend on the batch a frame lands in: every candidate's map
-value is computed by one thread in a fixed order, whatever else is batched.
+In FP32, results do not depend on the batch a frame lands in: each GCC sample
+and each candidate's map value is summed in a fixed order, whatever else is
+batched. In BF16/FP16 a frame's map runs on the vector-unit or the
+matrix-core kernel depending on how many frames of its array share the batch,
+so its results agree with those of the same frame served alone to the
+BF16/FP16 tolerance, not bit for bit.
 """
 from __future__ import annotations
 
@@ -65,9 +69,12 @@ class _Array:
 
 
 def footprint(geom_J, M, K, L, S, P, h_max, max_f=S.BATCH_MAX_F, slots=2, sample_bytes=4):
-    """Device bytes an array occupies in the server (geometry + its share of each slot)."""
-    slot = max_f * (M * L * 4 + M * K * 8 + P * K * 8 + S * sample_bytes + 16) + 4 * 256
-    geom = 24 * geom_J + 8 * K * (2 * h_max + 33) + 64 * P + 4096
+    """Device bytes an array occupies in the server (geometry + its share of each slot):
+    frames, per-microphone phasors (rows of K rounded up to 16 bins), samples and
+    peaks per slot; candidates, the two GCC phase tables and the pair tables."""
+    Kr = (K + 15) // 16 * 16
+    slot = max_f * (M * L * 4 + M * Kr * 8 + S * sample_bytes + 16) + 4 * 256
+    geom = 24 * geom_J + 2 * 8 * Kr * (2 * h_max + 34) + 64 * P + 4096
     return geom + slots * slot
 
 
@@ -244,19 +251,17 @@ class SrpServer:
         pinned host memory while requests wait (an allocation can stall the
         device for milliseconds)."""
         import torch
-        fr = ws = psi = xi = pk = 0
+        fr = ws = xi = pk = 0
         for a in self.arrays.values():
             F = self.max_f
             fr += F * a.M * a.L
-            ws += (F * a.M * a.K * 8 + 255) // 256 * 256
-            psi += F * a.P * a.K
+            ws += (a.g.workspace_bytes(F) + 255) // 256 * 256
             xi += F * a.S
             pk += F
         for slot in self.slots:
             slot.host(fr)
             slot.buf("frames", fr, torch.float32)
             slot.buf("ws", ws, torch.uint8)
-            slot.buf("psi", psi, torch.complex64)
             slot.buf("xi", xi, self.sample_dtype)
             slot.buf("peaks", 2 * pk, torch.int64)
             slot.buf("items", S.batched_workspace_bytes(len(self.arrays)), torch.uint8)
@@ -276,14 +281,14 @@ class SrpServer:
         if not take:
             return
         # arena layout of this batch
-        fr_off, ws_off, psi_off, xi_off, pk_off = 0, 0, 0, 0, 0
+        fr_off, ws_off, xi_off, pk_off = 0, 0, 0, 0
         plan = []
         for a, reqs in take:
             F = len(reqs)
-            plan.append((a, reqs, F, fr_off, ws_off, psi_off, xi_off, pk_off))
+            nws = a.g.workspace_bytes(F)
+            plan.append((a, reqs, F, fr_off, ws_off, nws, xi_off, pk_off))
             fr_off += F * a.M * a.L
-            ws_off += (F * a.M * a.K * 8 + 255) // 256 * 256
-            psi_off += F * a.P * a.K
+            ws_off += (nws + 255) // 256 * 256
             xi_off += F * a.S
             pk_off += F
         host = slot.host(fr_off)
@@ -294,7 +299,6 @@ class SrpServer:
                 r.status = "running"
         frames = slot.buf("frames", fr_off, torch.float32)
         ws = slot.buf("ws", ws_off, torch.uint8)
-        psi = slot.buf("psi", psi_off, torch.complex64)
         xi = slot.buf("xi", xi_off, self.sample_dtype)
         peaks = slot.buf("peaks", 2 * pk_off, torch.int64)
         item_ws = slot.buf("items", S.batched_workspace_bytes(len(plan)), torch.uint8)
@@ -303,13 +307,11 @@ class SrpServer:
         try:
             with torch.cuda.stream(slot.stream):
                 frames[:fr_off].copy_(host[:fr_off], non_blocking=True)
-                for a, reqs, F, fo, wo, po, xo, ko in plan:
+                for a, reqs, F, fo, wo, nws, xo, ko in plan:
                     fv = frames[fo:fo + F * a.M * a.L].view(F, a.M, a.L)
-                    pv = psi[po:po + F * a.P * a.K].view(F, a.P, a.K)
-                    S.cross_spectra(a.g, fv, out=pv, workspace=ws[wo:wo + F * a.M * a.K * 8],
-                                    stream=slot.stream)
                     xv = xi[xo:xo + F * a.S].view(F, a.S)
-                    S.gcc_samples(a.g, pv, out=xv, dtype=self.dtype, stream=slot.stream)
+                    S.gcc_samples_frames(a.g, fv, out=xv, dtype=self.dtype,
+                                         workspace=ws[wo:wo + nws], stream=slot.stream)
                     items.append((a.g, xo, F, None, peaks[2 * ko:2 * (ko + F)].view(F, 2)))
                     reqs_all.extend(reqs)
                 S.map_nyquist_batched(items, xi, item_ws, stream=slot.stream, dtype=self.dtype)

@@ -123,6 +123,74 @@ def test_gcc_samples(cases, name):
     assert np.abs(got - ref).max() <= 1e-5 * wl.L
 
 
+def _gaps_are_zero(g, xi):
+    full = xi.float().cpu().numpy()
+    gaps = np.ones(g.S, dtype=bool)
+    for o, w in zip(g.offsets[:-1], g.W):
+        gaps[o:o + w] = False
+    return bool(np.all(full[:, gaps] == 0.0))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_gcc_samples_frames(cases, name):
+    """Frames -> GCC samples in one call (FFT, PHAT phasors, cross-spectra formed
+    on chip) against the oracle's samples from the frames in float64, and against
+    the two-call path (srp_cross_spectra, srp_gcc_samples)."""
+    wl = cases[name]
+    g = _geom(wl)
+    fr = _frames(wl)
+    xi = srp.gcc_samples_frames(g, fr)
+    two = srp.gcc_samples(g, srp.cross_spectra(g, fr))
+    torch.cuda.synchronize()
+    ref = R.oracle_xi(wl, R.oracle_psi(wl))
+    got = srp.unpack_samples(g, xi)
+    assert _gaps_are_zero(g, xi)
+    assert _rel(got, ref).max() <= XI_TOL
+    assert np.abs(got - ref).max() <= 1e-5 * wl.L
+    assert _rel(got, srp.unpack_samples(g, two)).max() <= XI_TOL
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("dtype", ["bf16", "fp16"])
+def test_gcc_samples_frames_lowp_rounded(cases, name, dtype):
+    """BF16/FP16 samples of the fused call are its float32 samples rounded once."""
+    wl = cases[name]
+    g = _geom(wl)
+    fr = _frames(wl)
+    x32 = srp.gcc_samples_frames(g, fr)
+    xlo = srp.gcc_samples_frames(g, fr, dtype=dtype)
+    torch.cuda.synchronize()
+    assert xlo.dtype == srp.sample_torch_dtype(dtype)
+    assert torch.equal(x32.to(xlo.dtype), xlo)
+
+
+def test_silent_microphones_give_zero_phasors():
+    """A microphone whose frame is all zeros has Y = 0, so every pair with it has
+    psi = 0 (PHAT of a zero product) and zero GCC samples, also when it shares a
+    complex transform with a live microphone (mic 2 with mic 3) or is the odd
+    one out (mic 6 of 7)."""
+    wl = WL.make_custom(M=7, J_shape=(5, 4, 3), L=512, F=5, seed=21)
+    fr = wl.frames.copy()
+    fr[:, 2, :] = 0.0
+    fr[1:3, 6, :] = 0.0
+    wl.frames = fr
+    g = _geom(wl)
+    fr_d = _frames(wl)
+    psi = srp.cross_spectra(g, fr_d)
+    xi = srp.gcc_samples_frames(g, fr_d)
+    torch.cuda.synchronize()
+    psi_ref = R.oracle_psi(wl)
+    got = _c128(psi)
+    assert np.all(got[psi_ref == 0] == 0) and np.all(np.abs(got[psi_ref != 0]) > 0.99)
+    err = np.sqrt((np.abs(got - psi_ref) ** 2).sum(axis=(1, 2)) /
+                  (np.abs(psi_ref) ** 2).sum(axis=(1, 2)))
+    assert err.max() <= PSI_TOL
+    ref = R.oracle_xi(wl, psi_ref)
+    gx = srp.unpack_samples(g, xi)
+    assert np.all(gx[ref == 0] == 0)
+    assert _rel(gx, ref).max() <= XI_TOL
+
+
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("dtype", ["fp32", "fp64"])
 def test_nyquist_map_from_same_samples(cases, name, dtype):
@@ -198,7 +266,7 @@ def test_peaks_only_equals_map_argmax(cases):
     pipe = srp.SrpPipeline(g, wl.F, keep_map=False)
     fr = _frames(wl)
     _, pk1 = pipe.nyquist(fr)
-    xi = srp.gcc_samples(g, srp.cross_spectra(g, fr))
+    xi = srp.gcc_samples_frames(g, fr)  # the samples the pipeline's Nyquist path uses
     m, _ = srp.map_nyquist(g, xi, want_peaks=False)
     pk2 = srp.argmax(m)
     torch.cuda.synchronize()
@@ -398,6 +466,17 @@ def test_nyquist_frame_block_boundaries(many_frames, F, dtype):
     idx, _ = srp.decode_peaks(pk)
     np.testing.assert_array_equal(idx, np.argmax(got, axis=1))
     R.check_argmax(idx, ref, tol, label=f"frame-blocks/F{F}/{dtype}")
+
+
+@pytest.mark.parametrize("F", [127, 128, 129, 520])
+def test_gcc_samples_frames_frame_blocks(many_frames, F):
+    """Frame counts around the fused GCC kernel's 128-frame workgroups."""
+    wl, xi_ref = many_frames
+    g = _geom(wl)
+    xi = srp.gcc_samples_frames(g, _frames(wl)[:F])
+    torch.cuda.synchronize()
+    assert xi.shape == (F, g.S) and _gaps_are_zero(g, xi)
+    assert _rel(srp.unpack_samples(g, xi), xi_ref[:F]).max() <= XI_TOL
 
 
 @pytest.fixture(scope="module")

@@ -43,7 +43,8 @@ def test_noalloc_cross_spectra_equals_workspace_call():
 
 
 def test_noalloc_cross_spectra_rejects_oversize_before_running():
-    # 16 mics, K = 513: 64 MiB hold 1,022 frames of phasors, not 1,100
+    # 16 mics, K = 513 (phasor rows of Kr = 528 bins): 64 MiB hold 992 frames
+    # of phasors, not 1,100
     wl = WL.make_custom(M=16, J_shape=(3, 3, 3), L=1024, F=2, seed=23)
     g = _geom(wl)
     F = 1100
@@ -56,8 +57,11 @@ def test_noalloc_cross_spectra_rejects_oversize_before_running():
     torch.cuda.synchronize()
     assert bool((out == complex(3.0, 1.0)).all())
     # the largest batch that fits runs
-    Fmax = (64 << 20) // (8 * g.M * g.K)
-    assert Fmax == 1022
+    Kr = (g.K + 15) // 16 * 16
+    Fmax = (64 << 20) // (8 * g.M * Kr)
+    assert Fmax == 992
+    with pytest.raises(srp.SrpError):
+        srp.cross_spectra_noalloc(g, frames[:Fmax + 1], out[:Fmax + 1])
     ok = srp.cross_spectra_noalloc(g, frames[:Fmax], out[:Fmax])
     torch.cuda.synchronize()
     assert bool((ok == 0).all())  # zero frames: PHAT gives psi = 0
