@@ -143,6 +143,8 @@ void nyquist_mx2_kernel(MxArgs a, const T* __restrict__ xi, const RunRec* __rest
   __shared__ __attribute__((aligned(16))) T xs0[kTile];
   __shared__ __attribute__((aligned(16))) T xs1[kTile];
   __shared__ unsigned long long kbest[FB];
+  // epilogue blocks of one candidate tile per wave: 32 frames x 32 values
+  __shared__ float epi[CT == 1 ? NW * 32 * 33 : 1];
 
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -426,36 +428,68 @@ void nyquist_mx2_kernel(MxArgs a, const T* __restrict__ xi, const RunRec* __rest
   bool valid[CT];
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) valid[ct] = jw + 32 * ct + cl < a.J;
-  static_for(std::make_integer_sequence<int, FT>(), [&](auto ftc) __attribute__((always_inline)) {
-    constexpr int ft = decltype(ftc)::value;
+  if constexpr (CT == 1) {
+    // One candidate tile: each frame tile's 32 x 32 values go through the
+    // wave's own LDS block (row = frame, 33 words apart); lane l then scans
+    // frame l % 32 over candidates 16 (l / 32) .. + 15 in order, keeping the
+    // first maximum, and the two halves meet in the block's LDS max on the
+    // (value, -index) key.
+    float* ep = epi + wave * (32 * 33);
+    const int ef = lane & 31;
+    const int eh = lane >> 5;
+    static_for(std::make_integer_sequence<int, FT>(), [&](auto ftc) __attribute__((always_inline)) {
+      constexpr int ft = decltype(ftc)::value;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int fl = ft * 32 + 8 * (r >> 2) + 4 * g + (r & 3);
-      const int fg = f0 + fl;
-      float vv[CT];
-#pragma unroll
-      for (int ct = 0; ct < CT; ++ct) {
-        const float v = 2.0f * acc[ct][ft][r];
-        if (a.map && valid[ct] && fg < a.F) a.map[(size_t)fg * a.J + jw + 32 * ct + cl] = v;
-        vv[ct] = valid[ct] ? v : -__builtin_inff();
+      for (int r = 0; r < 16; ++r) {
+        const int fl = 8 * (r >> 2) + 4 * g + (r & 3);
+        const float v = 2.0f * acc[0][ft][r];
+        if (a.map && valid[0] && f0 + ft * 32 + fl < a.F)
+          a.map[(size_t)(f0 + ft * 32 + fl) * a.J + jw + cl] = v;
+        ep[fl * 33 + cl] = valid[0] ? v : -__builtin_inff();
       }
       if (a.keys) {
-        const float vmax = half_wave_fmax(CT == 2 ? fmaxf(vv[0], vv[CT - 1]) : vv[0]);
-        const unsigned long long h0 = __ballot(vv[0] == vmax);
-        const unsigned long long m0 = g ? (h0 >> 32) : (h0 & 0xffffffffull);
-        int first;
-        if (CT == 2) {
+        float best = -__builtin_inff();
+        int bi = 0;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const float v = ep[ef * 33 + 16 * eh + i];
+          if (v > best) {
+            best = v;
+            bi = i;
+          }
+        }
+        const int fl = ft * 32 + ef;
+        if (f0 + fl < a.F && best > -__builtin_inff())
+          atomicMax(&kbest[fl], peak_key(best, static_cast<unsigned>(jw + 16 * eh + bi)));
+      }
+    });
+  } else {
+    static_for(std::make_integer_sequence<int, FT>(), [&](auto ftc) __attribute__((always_inline)) {
+      constexpr int ft = decltype(ftc)::value;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int fl = ft * 32 + 8 * (r >> 2) + 4 * g + (r & 3);
+        const int fg = f0 + fl;
+        float vv[CT];
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+          const float v = 2.0f * acc[ct][ft][r];
+          if (a.map && valid[ct] && fg < a.F) a.map[(size_t)fg * a.J + jw + 32 * ct + cl] = v;
+          vv[ct] = valid[ct] ? v : -__builtin_inff();
+        }
+        if (a.keys) {
+          const float vmax = half_wave_fmax(fmaxf(vv[0], vv[CT - 1]));
+          const unsigned long long h0 = __ballot(vv[0] == vmax);
+          const unsigned long long m0 = g ? (h0 >> 32) : (h0 & 0xffffffffull);
           const unsigned long long h1 = __ballot(vv[CT - 1] == vmax);
           const unsigned long long m1 = g ? (h1 >> 32) : (h1 & 0xffffffffull);
-          first = m0 ? __builtin_ctzll(m0) : 32 + __builtin_ctzll(m1 | (1ull << 63));
-        } else {
-          first = __builtin_ctzll(m0 | (1ull << 63));
+          const int first = m0 ? __builtin_ctzll(m0) : 32 + __builtin_ctzll(m1 | (1ull << 63));
+          if (cl == 0 && fg < a.F && vmax > -__builtin_inff())
+            atomicMax(&kbest[fl], peak_key(vmax, static_cast<unsigned>(jw + first)));
         }
-        if (cl == 0 && fg < a.F && vmax > -__builtin_inff())
-          atomicMax(&kbest[fl], peak_key(vmax, static_cast<unsigned>(jw + first)));
       }
-    }
-  });
+    });
+  }
   if (a.keys) {
     __syncthreads();
     for (int i = tid; i < FB; i += 64 * NW) {
