@@ -269,29 +269,34 @@ void cached_map_kernel(CachedArgs a, const T* __restrict__ xi, const T* __restri
     handover();
   }
 
-  // epilogue: x2, optional map store, argmax (LDS max per frame, then one
-  // global 64-bit atomic per frame and workgroup)
+  // epilogue: x2, optional map store, argmax per frame tile through the
+  // wave's LDS block (the staging buffers are free: waves 0-1 use xs0, 2-3
+  // xs1, 4-5 ws0, 6-7 ws1), then the block's LDS max per frame and one global
+  // 64-bit atomic per frame and workgroup
+  constexpr int kEp = argmax_block_floats<kCCT>();
+  static_assert(kCWaves == 8 && FB * kCRow * sizeof(T) >= 2 * kEp * sizeof(float) &&
+                    JB * kCRow * sizeof(T) >= 2 * kEp * sizeof(float),
+                "two argmax blocks per staging buffer");
+  float* ep = reinterpret_cast<float*>(wave < 2 ? xs0 : wave < 4 ? xs1 : wave < 6 ? ws0 : ws1) +
+              (wave & 1) * kEp;
 #pragma unroll
   for (int ft = 0; ft < kCWT; ++ft) {
+    float v[kCCT][16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-      const int fl = (wf * kCWT + ft) * 32 + 8 * (k >> 2) + 4 * g + (k & 3);
-      const int fg = f0 + fl;
-      unsigned long long best = 0ull;
+      const int fg = f0 + (wf * kCWT + ft) * 32 + 8 * (k >> 2) + 4 * g + (k & 3);
 #pragma unroll
       for (int c = 0; c < kCCT; ++c) {
         const int64_t ci = jb + c * 32 + cl;
-        const float v = 2.0f * acc[c][ft][k];
-        if (ci < a.J && fg < a.F) {
-          if (a.map) a.map[(size_t)fg * a.J + ci] = v;
-          const unsigned long long key = peak_key(v, static_cast<unsigned>(ci));
-          best = key > best ? key : best;
-        }
+        v[c][k] = 2.0f * acc[c][ft][k];
+        if (a.map && ci < a.J && fg < a.F) a.map[(size_t)fg * a.J + ci] = v[c][k];
+        if (ci >= a.J) v[c][k] = -__builtin_inff();
       }
-      if (a.keys) {
-        best = half_wave_max(best);
-        if (cl == 0 && best) atomicMax(&kbest[fl], best);
-      }
+    }
+    if (a.keys) {
+      const unsigned long long key = tile_argmax_key<kCCT>(ep, v, jb);
+      const int fl = (wf * kCWT + ft) * 32 + cl;
+      if (key && f0 + fl < a.F) atomicMax(&kbest[fl], key);
     }
   }
   if (a.keys) {

@@ -320,6 +320,10 @@ void nyquist_f32_kernel(NyqArgs a, const RunRec* __restrict__ recs) {
   __shared__ __attribute__((aligned(16))) float xs0[FT * kBlk32];
   __shared__ __attribute__((aligned(16))) float xs1[FT * kBlk32];
   __shared__ unsigned long long kbest[FB];
+  // argmax blocks of the epilogue
+  constexpr int kEp = argmax_block_floats<CT>();
+  constexpr bool kEpInTiles = FT * kBlk32 >= (NW / 2) * kEp;
+  __shared__ __attribute__((aligned(16))) float epi[kEpInTiles ? 1 : NW * kEp];
 
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -412,28 +416,29 @@ void nyquist_f32_kernel(NyqArgs a, const RunRec* __restrict__ recs) {
       for (int ft = 0; ft < (COMP ? FT : 1); ++ft) acc[ct][ft] += hi[ct][ft];
   }
 
-  // epilogue: D[frame][cand], lane (cl, g), register r -> frame 8 (r / 4) + 4 g + r % 4
+  // epilogue: D[frame][cand], lane (cl, g), register r -> frame 8 (r / 4) + 4 g + r % 4.
+  // x2, optional map store, the argmax of each frame tile through the wave's
+  // LDS block (in the staging tiles, free after the last barrier, when half
+  // the waves fit in each; else an array of its own), then the block's LDS
+  // max per frame and one global 64-bit atomic per frame and workgroup
+  float* ep = kEpInTiles ? (wave < NW / 2 ? xs0 : xs1) + (wave % (NW / 2)) * kEp : epi + wave * kEp;
 #pragma unroll
   for (int ft = 0; ft < FT; ++ft) {
+    float v[CT][16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const int fl = ft * 32 + 8 * (r >> 2) + 4 * g + (r & 3);
-      const int fg = f0 + fl;
-      unsigned long long best = 0ull;
+      const int fg = f0 + ft * 32 + 8 * (r >> 2) + 4 * g + (r & 3);
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
         const int64_t ci = jb + ct * 32 + cl;
-        const float v = 2.0f * acc[ct][ft][r];
-        if (ci < a.J && fg < a.F) {
-          if (a.map) a.map[(size_t)fg * a.J + ci] = v;
-          const unsigned long long k = peak_key(v, static_cast<unsigned>(ci));
-          best = k > best ? k : best;
-        }
+        v[ct][r] = 2.0f * acc[ct][ft][r];
+        if (a.map && ci < a.J && fg < a.F) a.map[(size_t)fg * a.J + ci] = v[ct][r];
+        if (ci >= a.J) v[ct][r] = -__builtin_inff();
       }
-      if (a.keys) {
-        best = half_wave_max(best);
-        if (cl == 0 && best) atomicMax(&kbest[fl], best);
-      }
+    }
+    if (a.keys) {
+      const unsigned long long k = tile_argmax_key<CT>(ep, v, jb);
+      if (k && f0 + ft * 32 + cl < a.F) atomicMax(&kbest[ft * 32 + cl], k);
     }
   }
   if (a.keys) {

@@ -143,8 +143,12 @@ void nyquist_mx2_kernel(MxArgs a, const T* __restrict__ xi, const RunRec* __rest
   __shared__ __attribute__((aligned(16))) T xs0[kTile];
   __shared__ __attribute__((aligned(16))) T xs1[kTile];
   __shared__ unsigned long long kbest[FB];
-  // epilogue blocks of one candidate tile per wave: 32 frames x 32 values
-  __shared__ float epi[CT == 1 ? NW * 32 * 33 : 1];
+  // argmax blocks of the epilogue (one candidate tile per wave): in the
+  // staging buffers (free by then) when half the waves fit in each, else
+  // an array of their own
+  constexpr int kEp = argmax_block_floats<1>();
+  constexpr bool kEpInTiles = kTile * sizeof(T) >= (NW / 2) * kEp * sizeof(float);
+  __shared__ __attribute__((aligned(16))) float epi[CT == 1 && !kEpInTiles ? NW * kEp : 1];
 
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -429,38 +433,24 @@ void nyquist_mx2_kernel(MxArgs a, const T* __restrict__ xi, const RunRec* __rest
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) valid[ct] = jw + 32 * ct + cl < a.J;
   if constexpr (CT == 1) {
-    // One candidate tile: each frame tile's 32 x 32 values go through the
-    // wave's own LDS block (row = frame, 33 words apart); lane l then scans
-    // frame l % 32 over candidates 16 (l / 32) .. + 15 in order, keeping the
-    // first maximum, and the two halves meet in the block's LDS max on the
-    // (value, -index) key.
-    float* ep = epi + wave * (32 * 33);
-    const int ef = lane & 31;
-    const int eh = lane >> 5;
+    // one candidate tile: the argmax of each frame tile through the wave's LDS
+    // block, then the block's LDS max on the (value, -index) key per frame
+    float* ep = kEpInTiles ? reinterpret_cast<float*>(wave < NW / 2 ? xs0 : xs1) +
+                                 (wave % (NW / 2)) * kEp
+                           : epi + wave * kEp;
     static_for(std::make_integer_sequence<int, FT>(), [&](auto ftc) __attribute__((always_inline)) {
       constexpr int ft = decltype(ftc)::value;
+      float v[1][16];
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int fl = 8 * (r >> 2) + 4 * g + (r & 3);
-        const float v = 2.0f * acc[0][ft][r];
-        if (a.map && valid[0] && f0 + ft * 32 + fl < a.F)
-          a.map[(size_t)(f0 + ft * 32 + fl) * a.J + jw + cl] = v;
-        ep[fl * 33 + cl] = valid[0] ? v : -__builtin_inff();
+        const int fg = f0 + ft * 32 + 8 * (r >> 2) + 4 * g + (r & 3);
+        v[0][r] = 2.0f * acc[0][ft][r];
+        if (a.map && valid[0] && fg < a.F) a.map[(size_t)fg * a.J + jw + cl] = v[0][r];
+        if (!valid[0]) v[0][r] = -__builtin_inff();
       }
       if (a.keys) {
-        float best = -__builtin_inff();
-        int bi = 0;
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const float v = ep[ef * 33 + 16 * eh + i];
-          if (v > best) {
-            best = v;
-            bi = i;
-          }
-        }
-        const int fl = ft * 32 + ef;
-        if (f0 + fl < a.F && best > -__builtin_inff())
-          atomicMax(&kbest[fl], peak_key(best, static_cast<unsigned>(jw + 16 * eh + bi)));
+        const unsigned long long k = tile_argmax_key<1>(ep, v, jw);
+        if (k && f0 + ft * 32 + cl < a.F) atomicMax(&kbest[ft * 32 + cl], k);
       }
     });
   } else {

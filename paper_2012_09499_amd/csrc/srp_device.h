@@ -67,6 +67,49 @@ __device__ __forceinline__ unsigned long long half_wave_max(unsigned long long k
   return k;
 }
 
+// Per-frame argmax of one wave's 32-frame tile over its 32 NC candidates,
+// through LDS instead of cross-lane shuffles. The wave writes the values of
+// its NC matrix-core tiles (D layout of the 32x32 instructions: lane (cl, g),
+// register r holds frame 8 (r / 4) + 4 g + r % 4 and candidate 32 c + cl of
+// tile c) into its own block `ep` (32 rows of 32 NC + 1 floats); lane l then
+// scans frame l % 32 over candidates 16 NC (l / 32) .. 16 NC (l / 32 + 1) - 1
+// in order, keeping the first maximum. Returns the key (value, -index) of that
+// maximum, candidate cand0 + its offset, or 0 when every value scanned is
+// -inf. v[c][r]: the values, -inf for candidates past the end. Only the
+// calling wave uses `ep`, whose LDS operations run in program order.
+template <int NC>
+__device__ __forceinline__ unsigned long long tile_argmax_key(float* ep, const float (&v)[NC][16],
+                                                              int64_t cand0) {
+  constexpr int RS = 32 * NC + 1;
+  const int lane = threadIdx.x & 63;
+  const int cl = lane & 31;
+  const int g = lane >> 5;
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) ep[(8 * (r >> 2) + 4 * g + (r & 3)) * RS + 32 * c + cl] = v[c][r];
+  const float* row = ep + cl * RS + 16 * NC * g;
+  float best = -__builtin_inff();
+  int bi = 0;
+#pragma unroll
+  for (int i = 0; i < 16 * NC; ++i) {
+    const float x = row[i];
+    if (x > best) {
+      best = x;
+      bi = i;
+    }
+  }
+  return best > -__builtin_inff()
+             ? peak_key(best, static_cast<unsigned>(cand0 + 16 * NC * g + bi))
+             : 0ull;
+}
+
+// Floats of the per-wave LDS blocks of tile_argmax_key.
+template <int NC>
+constexpr int argmax_block_floats() {
+  return 32 * (32 * NC + 1);
+}
+
 __device__ __forceinline__ unsigned long long wave_max(unsigned long long k) {
   unsigned long long o = __shfl_xor(k, 32, 64);
   k = o > k ? o : k;
