@@ -22,7 +22,13 @@ candidate grids) arrive as requests. The server
 * validates each request (known, admitted array; frame shape; finite values)
   and fails that request alone on error; a failed batch launch fails only the
   requests of that batch;
-* records per-frame latency from arrival to observed completion.
+* records per-frame latency from arrival to observed completion and, given a
+  deadline, counts the frames that complete after it (and, if asked, fails
+  frames whose deadline has already passed when a batch is assembled instead
+  of computing them);
+* takes an optional fault hook, called with each batch's requests before its
+  device work is enqueued: an exception there fails that batch's requests
+  alone, as a failed launch would (used to test the failure path).
 
 In FP32, results do not depend on the batch a frame lands in: each GCC sample
 and each candidate's map value is summed in a fixed order, whatever else is
@@ -36,7 +42,7 @@ from __future__ import annotations
 import collections
 import dataclasses
 import time
-from typing import Dict, List, Optional
+from typing import Callable, Dict, List, Optional
 
 import numpy as np
 
@@ -51,6 +57,8 @@ class Request:
     t_arrival: float
     status: str = "pending"          # pending | running | done | failed
     t_done: float = 0.0
+    t_deadline: float = float("inf")
+    missed: bool = False             # done after its deadline
     peak_index: int = -1
     peak_value: float = float("nan")
     error: str = ""
@@ -109,7 +117,9 @@ class _Slot:
 class SrpServer:
     def __init__(self, memory_budget: Optional[int] = None, device="cuda:0",
                  max_frames_per_array: Optional[int] = None, slots: int = 2,
-                 dtype: str = "fp32"):
+                 dtype: str = "fp32", deadline_ms: Optional[float] = None,
+                 shed_expired: bool = False,
+                 fault_hook: Optional[Callable[[List[Request]], None]] = None):
         import torch
         if dtype not in ("fp32", "bf16", "fp16"):
             raise ValueError(f"dtype must be fp32, bf16 or fp16, not {dtype!r}")
@@ -130,6 +140,12 @@ class SrpServer:
         self.completed: List[Request] = []
         self.failed: List[Request] = []
         self.rejected = 0
+        self.deadline_s = None if deadline_ms is None else float(deadline_ms) * 1e-3
+        self.shed_expired = bool(shed_expired)
+        self.fault_hook = fault_hook
+        self.deadline_misses = 0
+        self.shed = 0
+        self.failed_batches = 0
         self.batches = 0
         self.batch_frames: List[int] = []
         self._seq = 0
@@ -188,6 +204,8 @@ class SrpServer:
     def submit(self, array_id, frame, t_arrival: Optional[float] = None) -> Request:
         t = time.perf_counter() if t_arrival is None else t_arrival
         r = Request(array_id, self._seq, frame, t)
+        if self.deadline_s is not None:
+            r.t_deadline = t + self.deadline_s
         self._seq += 1
         a = self.arrays.get(array_id)
         err = ""
@@ -240,6 +258,9 @@ class SrpServer:
                         r.peak_index = int(pk[i, 0])
                         r.peak_value = float(pk[i:i + 1].view(np.int32)[0, 2].view(np.float32))
                         r.frame = None
+                        if now > r.t_deadline:
+                            r.missed = True
+                            self.deadline_misses += 1
                         self.completed.append(r)
                         n += 1
                 slot.event, slot.requests = None, []
@@ -274,10 +295,21 @@ class SrpServer:
     def _launch(self, slot: _Slot):
         import torch
         take = []
+        now = time.perf_counter()
         for a in self.arrays.values():
-            if a.pending:
-                k = min(len(a.pending), self.max_f)
-                take.append((a, [a.pending.popleft() for _ in range(k)]))
+            reqs = []
+            while a.pending and len(reqs) < self.max_f:
+                r = a.pending.popleft()
+                if self.shed_expired and now > r.t_deadline:
+                    # its deadline has passed: failed without computing it
+                    r.status, r.error, r.t_done = "failed", "deadline passed", now
+                    r.frame = None
+                    self.failed.append(r)
+                    self.shed += 1
+                    continue
+                reqs.append(r)
+            if reqs:
+                take.append((a, reqs))
         if not take:
             return
         # arena layout of this batch
@@ -305,6 +337,8 @@ class SrpServer:
         items = []
         reqs_all = []
         try:
+            if self.fault_hook is not None:
+                self.fault_hook([r for _, reqs, *_ in plan for r in reqs])
             with torch.cuda.stream(slot.stream):
                 frames[:fr_off].copy_(host[:fr_off], non_blocking=True)
                 for a, reqs, F, fo, wo, nws, xo, ko in plan:
@@ -324,9 +358,11 @@ class SrpServer:
                 ev = torch.cuda.Event()
                 ev.record(slot.stream)
         except Exception as e:  # a failed launch fails this batch only
+            self.failed_batches += 1
             for _, reqs, *_ in plan:
                 for r in reqs:
                     r.status, r.error, r.t_done = "failed", str(e), time.perf_counter()
+                    r.frame = None
                     self.failed.append(r)
             return
         slot.peaks_host = ph.numpy()
@@ -342,7 +378,12 @@ class SrpServer:
                           for r in self.completed if r.array_id in self.arrays))
         return {
             "frames_done": len(self.completed), "frames_failed": len(self.failed),
-            "rejected_requests": self.rejected,
+            "rejected_requests": self.rejected, "failed_batches": self.failed_batches,
+            "deadline_ms": None if self.deadline_s is None else self.deadline_s * 1e3,
+            "deadline_misses": self.deadline_misses,
+            "deadline_miss_rate": (self.deadline_misses / len(self.completed)
+                                   if self.completed else 0.0),
+            "shed_expired": self.shed,
             "frames_per_s": len(self.completed) / t_span,
             "cand_pair_evals_per_s": evals / t_span,
             "latency_ms_p50": float(np.percentile(lat, 50)) if lat.size else None,

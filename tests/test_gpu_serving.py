@@ -10,6 +10,9 @@
   every frame the same peak as the frame processed alone (bit-identical in
   FP32; in BF16 within the BF16 tolerance, since the kernel a frame runs on
   depends on how many frames of its array share its batch).
+* A fault injected into one batch's launch fails that batch alone; frames
+  done after their deadline are counted, and with shedding a frame whose
+  deadline passed before its batch is failed without running.
 """
 import time
 
@@ -244,3 +247,57 @@ def test_server_poisson_stream_runs_and_reports():
     st = srv.stats(time.perf_counter() - t0)
     assert st["frames_done"] == len(arrivals) and st["frames_failed"] == 0
     assert st["latency_ms_p99"] >= st["latency_ms_p50"] > 0
+
+
+def test_server_injected_batch_failure_fails_only_that_batch():
+    """A fault injected into the second batch's launch fails that batch's frames
+    alone: the batches before and after it complete, and a frame served after
+    the failure gives the same peak as before it (FP32: bit-identical)."""
+    wls = _arrays()[:2]
+    batches = []
+
+    def hook(reqs):
+        batches.append(len(reqs))
+        if len(batches) == 2:
+            raise RuntimeError("injected launch failure")
+
+    srv = SV.SrpServer(fault_hook=hook)
+    for i, w in enumerate(wls):
+        assert srv.open_array(i, w.mic_xyz, w.candidates(), fs=w.fs, L=w.L, c=w.c,
+                              n_aux=w.n_aux, field=w.field)
+
+    def wave():
+        reqs = [srv.submit(i, w.frames[0]) for i, w in enumerate(wls)]
+        srv.drain()
+        return reqs
+
+    first, second, third = wave(), wave(), wave()
+    assert len(batches) == 3
+    assert all(r.status == "done" for r in first + third)
+    assert all(r.status == "failed" and "injected" in r.error for r in second)
+    for a, b in zip(first, third):
+        assert (a.peak_index, a.peak_value) == (b.peak_index, b.peak_value)
+    st = srv.stats(1.0)
+    assert st["failed_batches"] == 1 and st["frames_failed"] == len(second)
+    assert st["frames_done"] == len(first) + len(third)
+
+
+def test_server_deadline_accounting_and_shedding():
+    """Frames done after their deadline are counted; with shedding, a frame whose
+    deadline has passed before its batch is assembled fails without running."""
+    w = _arrays()[0]
+    srv = SV.SrpServer(deadline_ms=1e-3)  # 1 us: every frame misses it
+    assert srv.open_array(0, w.mic_xyz, w.candidates(), fs=w.fs, L=w.L, c=w.c, n_aux=w.n_aux)
+    reqs = [srv.submit(0, w.frames[0]) for _ in range(3)]
+    srv.drain()
+    assert all(r.status == "done" and r.missed for r in reqs)
+    st = srv.stats(1.0)
+    assert st["deadline_misses"] == 3 and st["deadline_miss_rate"] == 1.0
+    shed = SV.SrpServer(deadline_ms=50.0, shed_expired=True)
+    assert shed.open_array(0, w.mic_xyz, w.candidates(), fs=w.fs, L=w.L, c=w.c, n_aux=w.n_aux)
+    late = shed.submit(0, w.frames[0], t_arrival=time.perf_counter() - 1.0)
+    fresh = shed.submit(0, w.frames[0])
+    shed.drain()
+    assert late.status == "failed" and late.error == "deadline passed"
+    assert fresh.status == "done" and not fresh.missed
+    assert shed.stats(1.0)["shed_expired"] == 1
