@@ -167,20 +167,23 @@ void nyquist_mx2_kernel(MxArgs a, const T* __restrict__ xi, const RunRec* __rest
   const double qx = a.cand[oc], qy = a.cand[a.J + oc], qz = a.cand[2 * a.J + oc];
   for (int i = tid; i < FB; i += 64 * NW) kbest[i] = 0ull;
 
-  // staging: the tile holds, for each pair j of 16-byte chunks (16 lags), the
-  // 32-byte pieces of all FB rows: element (j FB + row) 16 + e. One copy
-  // instruction moves one chunk pair of 32 rows (lane i: row 32 G + i / 2,
-  // chunk 2 j + i % 2), landing as 1 KB of contiguous LDS; wave w copies the
-  // row groups G = w, w + NW, ... Rows at or past F repeat the last frame (their
+  // staging: the tile holds, for each pair j of 16-byte chunks (16 lags) and
+  // each group G of 32 rows, the first chunks of the 32 rows, then their second
+  // chunks: element (j FB + 32 G) 16 + (r + 32 h) 8 + e for row 32 G + r,
+  // chunk 2 j + h. One copy instruction moves one chunk pair of 32 rows (lane
+  // i: row 32 G + i % 32, chunk 2 j + i / 32), landing as 1 KB of contiguous
+  // LDS, and a step's fragment read (lane (cl, g): row cl, chunk g) is then
+  // 1 KB read in lane order, free of bank conflicts; wave w copies the row
+  // groups G = w, w + NW, ... Rows at or past F repeat the last frame (their
   // outputs are discarded); a chunk past the run repeats its last chunk (its
   // weights are zero). Only the chunk pairs the run's steps read are copied.
   constexpr int kGroups = FT;                             // 32-row groups of the tile
   constexpr int kGpw = (kGroups + NW - 1) / NW;           // groups per wave
-  const int sub = lane & 1;
+  const int sub = lane >> 5;
   unsigned roff[kGpw];
 #pragma unroll
   for (int k = 0; k < kGpw; ++k) {
-    const int row = 32 * (wave + NW * k) + (lane >> 1);
+    const int row = 32 * (wave + NW * k) + (lane & 31);
     const int rr = row < nrows ? row : nrows - 1;
     roff[k] = static_cast<unsigned>(rr) * static_cast<unsigned>(a.S) * sizeof(T);
   }
@@ -301,7 +304,7 @@ void nyquist_mx2_kernel(MxArgs a, const T* __restrict__ xi, const RunRec* __rest
         u0[ct] = static_cast<float>(ia) + xf[ct];
       }
     }
-    const T* tbase = tile + cl * 16 + 8 * g;
+    const T* tbase = tile + (cl + 32 * g) * 8;
     // (steps past the run re-read its last step and are never contracted)
     auto frag_addr = [&](int s) __attribute__((always_inline)) {
       const int sc = s < steps ? s : steps - 1;
