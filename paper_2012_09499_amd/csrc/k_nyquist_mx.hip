@@ -3,27 +3,25 @@
 // with float32 accumulation:
 //   map[f][i] = 2 sum_p sum_{|n| <= h_p} xi_p(nT) sinc(x_p(i) - n).
 //
-// Layout. A workgroup is 4 waves, one per SIMD, and owns 128 candidates x up
-// to 512 frames. Each wave owns 32 candidates and ALL the workgroup's frames
-// (FT 32-frame tiles, FT <= 16): every weight a lane forms feeds FT matrix-core
-// instructions, and the FT accumulator tiles (16 FT registers per lane, 256 at
-// FT = 16) live in the accumulation registers (one wave per SIMD leaves the
-// SIMD's whole register file to it). One step consumes 16 lags: lane (cl, g)
-// (cl = lane % 32, g = lane / 32) holds lags 8g .. 8g+7 of the step for frame
-// cl of every frame tile (A = samples, one 16-byte LDS read per tile) and for
-// candidate cl (B = weights, formed in registers).
+// Layout. A workgroup is 8 waves, two per SIMD, and owns 256 candidates x up
+// to 256 frames. Each wave owns 32 candidates and ALL the workgroup's frames
+// (FT 32-frame tiles, FT <= 8): every weight a lane forms feeds FT
+// matrix-core instructions, and the FT accumulator tiles take 16 FT registers
+// per lane. One step consumes 16 lags: lane (cl, g) (cl = lane % 32,
+// g = lane / 32) holds lags 8g .. 8g+7 of the step for frame cl of every frame
+// tile (A = samples, one 16-byte LDS read per tile) and for candidate cl
+// (B = weights, formed in registers).
 //
 // Samples. Each lag run (<= 64 lags of one pair window, lagrun records of the
-// geometry) is copied into LDS as [frames][64 lags] with 16-byte global-to-LDS
-// copies issued by all four waves, double-buffered: the next run's copies are
-// in flight while the current run is contracted. 16-byte chunk c of row r is
-// stored at chunk c ^ ((r >> 1) & 7) (16 consecutive rows of a step's read hit
-// 8 different chunk positions per row parity: no bank conflicts). The copy
-// offsets of a lane are fixed for the whole kernel except for one per-run
-// chunk clamp; a chunk past the run repeats the run's last chunk and its
-// weights are zeroed instead (a run's last chunk ends at its window's end, and
-// the columns between the window's end and the chunk's end are the sample
-// layout's zero gap).
+// geometry) is copied into LDS with 16-byte global-to-LDS copies issued by all
+// waves, double-buffered: the next run's copies are in flight while the
+// current run is contracted. For each pair of 16-byte chunks and each group of
+// 32 rows, the tile holds the rows' first chunks, then their second chunks, so
+// one copy instruction lands as 1 KB of contiguous LDS and a step's fragment
+// read is 1 KB read in lane order. A chunk past the run repeats the run's last
+// chunk and its weights are zeroed instead (a run's last chunk ends at its
+// window's end, and the columns between the window's end and the chunk's end
+// are the sample layout's zero gap).
 //
 // Weights. x = xi + xf with xi = rint(x) and the fraction xf rounded to the
 // grid 2^-e, e chosen per geometry so that every sinc denominator
@@ -70,6 +68,12 @@ template <> struct Mx32<_Float16> {
 constexpr int kTiles = 1;
 constexpr int kWavesPerBlock = 8;
 constexpr int kRow = kNyqRunMax;     // elements per LDS row (64 lags)
+// LDS reads of the next step's fragments issued after each of a step's first
+// matrix-core instructions, and vector instructions slotted after each
+// (measured at the room scale and at 32 microphones against groups of 2 and 8
+// and 3 vector instructions: within 1 %, this the fastest).
+constexpr int kMxReadGroup = 4;
+constexpr int kMxValuPerMfma = 4;
 
 struct MxArgs {
   const double* cand;      // [3][J]
@@ -87,13 +91,6 @@ struct MxArgs {
   float* map;              // [F][J] or null
   unsigned long long* keys;  // peaks viewed as u64 pairs, or null
 };
-
-// Register sets of the sample-read ring: the largest divisor of FT up to 8.
-constexpr int ring_size(int ft) {
-  int r = ft < 8 ? ft : 8;
-  while (ft % r != 0) --r;
-  return r;
-}
 
 // sin(pi x) / pi for |x| <= 1/2 in float32: the Taylor series of sin,
 // x sum_k (-1)^k pi^(2k) x^(2k) / (2k+1)!, truncated after x^13 (truncation
@@ -348,66 +345,68 @@ void nyquist_mx2_kernel(MxArgs a, const T* __restrict__ xi, const RunRec* __rest
         }
       }
     };
-    // Software pipeline: a ring of kRing sample fragments, the read of
-    // fragment q + kRing issued right after the instructions that consumed
-    // fragment q (the ring size divides FT, so a fragment's slot is the same
-    // in every step); the next step's weights are formed between this step's
-    // matrix-core instructions.
-    constexpr int kRing = ring_size(FT);
-    vec8 ring[kRing];
+    // Software pipeline: two register sets of a step's FT sample fragments.
+    // A step contracts one set while the next step's fragments are read into
+    // the other, those reads issued in groups of kMxReadGroup right after the
+    // step's first matrix-core instructions; the next step's weights are
+    // formed between the matrix-core instructions. (While a run's copies into
+    // the other staging buffer are in flight, the compiler waits for all LDS
+    // reads before the first matrix-core instruction of a step rather than
+    // for the fragment it needs; with the reads issued early in the previous
+    // step, that wait finds them done.)
+    vec8 ra[FT], rb[FT];
     {
       const T* src = frag_addr(0);
 #pragma unroll
-      for (int i = 0; i < kRing; ++i) ring[i] = read(src, i);
+      for (int i = 0; i < FT; ++i) ra[i] = read(src, i);
     }
-    auto step = [&](const vec8 (&wc)[CT], const T* cur, const T* nxt) __attribute__((always_inline)) {
+    // (reads: whether to read the next step's fragments from nxt)
+    auto step = [&](auto reads, const vec8 (&wc)[CT], const vec8 (&rc)[FT], vec8 (&rn)[FT],
+                    const T* nxt) __attribute__((always_inline)) {
+      constexpr bool kReads = decltype(reads)::value;
 #pragma unroll
-      for (int i = 0; i < FT; ++i) {
+      for (int i = 0; i < FT; ++i)
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct)
-          acc[ct][i] = Mx32<T>::mfma(ring[i % kRing], wc[ct], acc[ct][i]);
-        const int q = i + kRing;  // fragment read into the freed slot
-        ring[i % kRing] = q < FT ? read(cur, q) : read(nxt, q - FT);
-      }
-      // issue order per fragment: a matrix-core instruction, the LDS read
-      // into the slot the fragment frees, vector instructions, the second
-      // matrix-core instruction, vector instructions
+          acc[ct][i] = Mx32<T>::mfma(rc[i], wc[ct], acc[ct][i]);
+      if (kReads) {
 #pragma unroll
-      for (int i = 0; i < FT; ++i) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
-        if (CT == 2) {
-          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-          __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
-        }
+        for (int i = 0; i < FT; ++i) rn[i] = read(nxt, i);
       }
+      // issue order: per fragment the matrix-core instruction(s) of its
+      // tiles, then (for the first fragments) a group of reads, then vector
+      // instructions
+      static_for(std::make_integer_sequence<int, FT>(), [&](auto ic) __attribute__((always_inline)) {
+        constexpr int i = decltype(ic)::value;
+        constexpr int left = FT - i * kMxReadGroup;  // reads not yet placed
+        __builtin_amdgcn_sched_group_barrier(0x008, CT, 0);
+        if constexpr (kReads && left > 0)
+          __builtin_amdgcn_sched_group_barrier(0x100, left < kMxReadGroup ? left : kMxReadGroup, 0);
+        __builtin_amdgcn_sched_group_barrier(0x002, kMxValuPerMfma * CT, 0);
+      });
     };
-    // read addresses first (scheduling barriers keep them ahead), then each
-    // step's instructions with the next step's weights slotted between them
-    // (the addresses are recomputed from the tile every iteration rather than
-    // carried across iterations: a pointer that the loop carries hides which
-    // staging buffer it points into, and the compiler then waits for the other
-    // buffer's copies in flight before reading)
+    // each step's instructions with the next step's weights slotted between
+    // them (the read addresses are recomputed from the tile every iteration
+    // rather than carried across iterations: a pointer that the loop carries
+    // hides which staging buffer it points into, and the compiler then waits
+    // for the other buffer's copies in flight before reading)
+    typedef std::integral_constant<bool, true> WithReads;
+    typedef std::integral_constant<bool, false> NoReads;
     vec8 w0[CT], w1[CT];
     weights(0, w0);
     int s = 0;
     for (; s + 1 < steps; s += 2) {
-      const T* p0 = frag_addr(s);
       const T* p1 = frag_addr(s + 1);
       const T* p2 = frag_addr(s + 2);
       __builtin_amdgcn_sched_barrier(0);
       weights(s + 1, w1);
-      step(w0, p0, p1);
+      step(WithReads(), w0, ra, rb, p1);
       __builtin_amdgcn_sched_barrier(0);
       weights(s + 2, w0);
-      step(w1, p1, p2);
+      step(WithReads(), w1, rb, ra, p2);
       __builtin_amdgcn_sched_barrier(0);
     }
-    if (s < steps) {
-      const T* p0 = frag_addr(s);
-      step(w0, p0, p0);
-    }
+    if (s < steps) step(NoReads(), w0, ra, rb, frag_addr(s));
   };
 
   stage(recs[0], xs0);
