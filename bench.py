@@ -389,6 +389,34 @@ def next_rows_leg(srp, torch, wl, g, frames, pipe, steps):
     return res
 
 
+def library_gemm_reference(torch, dev, n: int = 8192, reps: int = 10):
+    """Rate of the vendor library's dense GEMM (torch.matmul -> hipBLASLt) on
+    n x n x n operands per dtype, timed on the same device: the rate a plain
+    matrix product reaches on this chip under its real clock and power limits,
+    a practical ceiling to read the map kernels' utilisation against (the
+    roofline itself keeps the published peak)."""
+    res = {"n": n, "library": "torch.matmul (hipBLASLt)"}
+    for name, dt in (("bf16", torch.bfloat16), ("fp16", torch.float16), ("fp32", torch.float32)):
+        gen = torch.Generator(device=dev).manual_seed(0)
+        a = torch.randn(n, n, device=dev, dtype=dt, generator=gen)
+        b = torch.randn(n, n, device=dev, dtype=dt, generator=gen)
+        for _ in range(3):
+            c = a @ b
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            c = a @ b
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[f"{name}_tflops"] = 2.0 * n ** 3 / (ms * 1e-3) / 1e12
+        del a, b, c
+    torch.cuda.empty_cache()
+    return res
+
+
 def _timed(step, steps: int, n_marks: int):
     """Run `step(events)` `steps` times after one untimed call; return the wall
     ms per step and the mean ms between consecutive HIP-event marks."""
@@ -472,6 +500,8 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--conv-steps", type=int, default=3)
     ap.add_argument("--no-conventional", action="store_true")
+    ap.add_argument("--no-gemm-reference", action="store_true",
+                    help="skip timing the library GEMM reference (practical matrix-core ceiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-other-geometries", action="store_true",
                     help="skip the 32-mic and 64-mic Nyquist legs")
@@ -811,6 +841,28 @@ def main():
                   f"{st['offered_frames_per_s']:.0f} offered, p50 {st['latency_ms_p50']:.1f} ms, "
                   f"p99 {st['latency_ms_p99']:.1f} ms, {100 * st['deadline_miss_rate']:.1f} % past "
                   f"the {st['deadline_ms']:.0f} ms deadline", file=sys.stderr, flush=True)
+
+    if not args.no_gemm_reference:
+        # the library GEMM's rate on this chip: each matrix-core leg's
+        # algorithmic rate is also stated as a fraction of it
+        ref = library_gemm_reference(torch, dev)
+        out["library_gemm_reference"] = ref
+        for key, leg in [("roofline", out["roofline"])] + [
+                (k, v) for k, v in out.items()
+                if k.startswith(("nyquist_", "conventional")) and isinstance(v, dict)]:
+            ach = leg.get("achieved", leg.get("achieved_tflops", leg.get("algorithmic_tflops")))
+            if ach is None:
+                continue
+            dt = "fp32" if key in ("roofline", "conventional") else (
+                "fp16" if key.endswith("fp16") else "bf16")
+            leg["frac_of_library_gemm"] = ach / ref[f"{dt}_tflops"]
+        for key in ("precision_32mic", "largest_64mic"):
+            for dt, leg in out.get(key, {}).items():
+                if dt in ("fp32", "bf16", "fp16") and "achieved_tflops" in leg:
+                    leg["frac_of_library_gemm"] = leg["achieved_tflops"] / ref[f"{dt}_tflops"]
+        print(f"[bench] library GEMM {ref['n']}^3: bf16 {ref['bf16_tflops']:.0f}, fp16 "
+              f"{ref['fp16_tflops']:.0f}, fp32 {ref['fp32_tflops']:.0f} TFLOP/s", file=sys.stderr,
+              flush=True)
 
     print(json.dumps(out), flush=True)
 
