@@ -786,7 +786,18 @@ def main():
         for dt in ("fp32", "bf16", "fp16"):
             m, _ = keep.nyquist(frames, dtype=dt)
             maps[dt] = m[:, sel].cpu().numpy().astype(np.float64)
-        del keep
+        if "skipped" not in out.get("nyquist_bf16_cached", {"skipped": ""}):
+            # the cached-weight map of the same frames (W built again)
+            xi_c = srp.gcc_samples_frames(g, frames, dtype="bf16", workspace=keep.workspace)
+            del keep
+            torch.cuda.empty_cache()
+            W = srp.nyquist_weights(g, "bf16")
+            m, _ = srp.map_nyquist_cached(g, W, xi_c, dtype="bf16", want_peaks=False)
+            maps["bf16_cached"] = m[:, sel].cpu().numpy().astype(np.float64)
+            del W, m, xi_c
+            torch.cuda.empty_cache()
+        else:
+            del keep
         e = {}
         for dt, sub in maps.items():
             r = np.sqrt(((sub - ref) ** 2).sum(1) / (ref ** 2).sum(1))

@@ -483,7 +483,7 @@ def test_gcc_samples_frames_frame_blocks(many_frames, F):
 def wide_grid():
     # 76,800 candidates (300 blocks of 256) x 300 frames: 600 workgroups of
     # 256 candidates x 256 frames, which on a 256-CU device fill two whole
-    # rounds (one workgroup per CU in FP32, two in BF16/FP16) and leave 44
+    # rounds (one workgroup per CU, in every precision) and leave 44
     # candidate blocks, so the map call runs as two launches split at candidate
     # 65,536 (the rest with 64-frame blocks, the last of them 44 frames)
     wl = WL.make_custom(M=8, J_shape=(80, 40, 24), L=256, F=300, seed=12)
