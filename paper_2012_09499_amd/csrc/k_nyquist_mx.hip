@@ -61,13 +61,13 @@ template <> struct Mx32<_Float16> {
 };
 
 // Launch shape: candidate tiles per wave and waves per workgroup (a multiple
-// of the 4 SIMDs of a CU). One tile per wave and two waves per SIMD: the two
-// waves of a SIMD overlap each other's vector work, waits and barriers with
-// the matrix cores (measured at the room scale: 5.1 ms per call, against 5.6
-// ms for two tiles per wave and one wave per SIMD).
+// of the 4 SIMDs of a CU). One tile per wave and two waves per SIMD in one
+// workgroup: the two waves of a SIMD overlap each other's vector work and
+// waits with the matrix cores (measured at the room scale: 4.54 ms per call,
+// against 5.72 ms for two tiles per wave and one wave per SIMD, and 5.17 ms
+// for two 4-wave workgroups per CU, which copy every run twice per CU).
 constexpr int kTiles = 1;
 constexpr int kWavesPerBlock = 8;
-constexpr int kRow = kNyqRunMax;     // elements per LDS row (64 lags)
 // LDS reads of the next step's fragments issued after each of a step's first
 // matrix-core instructions, and vector instructions slotted after each
 // (measured at the room scale and at 32 microphones against groups of 2 and 8
