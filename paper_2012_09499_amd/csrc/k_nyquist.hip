@@ -220,14 +220,14 @@ __device__ __forceinline__ void nyq_prepare(const NyqArgs& a, const RunRec& run,
                                             LaneState<CT>& st, int g) {
   if (run.len <= 0) return;
   if (run.p != st.cur_p) pair_setup<CT>(a, run, st);
-  // this lane's first lag in the run: n = -h + t0 + g
+  // this lane's first lag in the run: n = -h + t0 + 2g (lane g takes lags
+  // 4k + 2g and 4k + 2g + 1 of chunk k, at the run's even and odd steps)
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) {
-    const int ia = st.xr[ct] + run.h - run.t0 - g;
+    const int ia = st.xr[ct] + run.h - run.t0 - 2 * g;
     st.dnum[ct] = static_cast<float>(ia);
     st.qv[ct] = (ia & 1) ? -st.sp[ct] : st.sp[ct];
     st.w0[ct] = st.qv[ct] * __builtin_amdgcn_rcpf(st.dnum[ct] + st.xf[ct]);
-    st.dnum[ct] -= 2.0f;
   }
 }
 
@@ -243,66 +243,102 @@ __device__ __forceinline__ void nyq_run(const RunRec& run, LaneState<CT>& st, co
     dnum[ct] = st.dnum[ct];
     qv[ct] = st.qv[ct];
   }
-  // lag t = 2 s + g of row R: chunk (s >> 1) ^ (R & 15), element 2 (s & 1) + g;
-  // R & 15 = cl & 15 in every frame tile
-  const float* arow = tile + cl * kRow32 + g;
+  // Lags of row R: step s takes, from chunk k = s >> 1 (stored at chunk
+  // k ^ (R & 15)), lag 4k + (s & 1) in the lanes g = 0 and lag 4k + 2 + (s & 1)
+  // in the lanes g = 1, so a lane reads its two lags of a chunk (elements 2g,
+  // 2g + 1) with one 8-byte LDS read for the chunk's two steps. R & 15 = cl & 15
+  // in every frame tile. Over the two steps of a chunk the matrix cores sum all
+  // four of its lags. The step count covers every lag of the run: a run's
+  // length is a multiple of 8 or its window's end, and the lags of the last
+  // chunk past that end read the sample layout's zero gap (with finite weights:
+  // a denominator is never an integer).
+  const float* arow = tile + cl * kRow32 + 2 * g;
   const int swz4 = (cl & 15) << 2;  // the row's chunk swizzle, in floats
-  const int steps = (run.len + 1) >> 1;
-  // software pipeline, two steps per iteration with ping-pong operand sets:
-  // the LDS samples and weights of the next step are fetched and formed while
-  // the matrix cores work on the current one. Steps 2k and 2k + 1 read the
-  // same chunk (elements 0 + g and 2 + g); a read past the run (the pipeline's
-  // look-ahead after its last step) stays inside the row and is never used.
-  float av0[FT], av1[FT], w0[CT], w1[CT];
-  auto load = [&](const float* src, float (&av)[FT]) {
+  const int steps = (run.len & 3) == 2 ? ((run.len >> 2) + 1) << 1 : (run.len + 1) >> 1;
+  // software pipeline over chunks with ping-pong operand sets: the next
+  // chunk's samples are read while the matrix cores work on the current one
+  // (a read past the run stays inside the row and is never used); each step's
+  // weight is formed while the previous step's matrix-core instructions run.
+  // Even steps: (-1)^n sin(pi xf) / pi / (dnum + xf); odd steps the lag one
+  // further: the opposite sign and dnum - 1; the next chunk: dnum - 4.
+  float2 avA[FT], avB[FT];
+  float we[CT], wo[CT];
+  auto chunk_src = [&](int k) { return arow + (((k & 15) << 2) ^ swz4); };
+  auto load = [&](const float* src, float2 (&av)[FT]) {
 #pragma unroll
-    for (int ft = 0; ft < FT; ++ft) av[ft] = src[ft * kBlk32];
+    for (int ft = 0; ft < FT; ++ft) av[ft] = *reinterpret_cast<const float2*>(src + ft * kBlk32);
   };
-  auto weights = [&](float (&w)[CT]) {
+  auto weight_odd = [&]() {
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+      wo[ct] = -qv[ct] * __builtin_amdgcn_rcpf((dnum[ct] - 1.0f) + st.xf[ct]);
+  };
+  auto weight_even_next = [&]() {
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
-      w[ct] = qv[ct] * __builtin_amdgcn_rcpf(dnum[ct] + st.xf[ct]);
-      dnum[ct] -= 2.0f;
+      dnum[ct] -= 4.0f;
+      we[ct] = qv[ct] * __builtin_amdgcn_rcpf(dnum[ct] + st.xf[ct]);
     }
   };
-  auto contract = [&](const float (&av)[FT], const float (&w)[CT]) {
+  auto contract = [&](const float2 (&av)[FT], bool odd, const float (&w)[CT]) {
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
       for (int ft = 0; ft < FT; ++ft)
-        acc[ct][ft] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[ft], w[ct], acc[ct][ft], 0, 0, 0);
+        acc[ct][ft] = __builtin_amdgcn_mfma_f32_32x32x2f32(odd ? av[ft].y : av[ft].x, w[ct],
+                                                          acc[ct][ft], 0, 0, 0);
   };
-  auto order = [&]() {
-    // issue order: one matrix-core instruction (its operands were read a
-    // half-iteration earlier), the read address, the next step's LDS reads,
-    // then the other matrix-core instructions with the weight arithmetic
-    // slotted between them
+  auto order = [&](bool reads) {
+    // issue order: one matrix-core instruction (its operands were read or
+    // formed earlier), then (at a chunk's even step) the next chunk's LDS
+    // reads, then the other matrix-core instructions with the weight
+    // arithmetic slotted between them
     __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
     __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
-    __builtin_amdgcn_sched_group_barrier(0x100, FT, 0);
+    if (reads) __builtin_amdgcn_sched_group_barrier(0x100, FT, 0);
 #pragma unroll
     for (int i = 1; i < CT * FT; ++i) {
       __builtin_amdgcn_sched_group_barrier(0x002, 1, 0);
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
     }
   };
-  const float* src = arow + swz4;  // chunk 0
-  load(src, av0);
+  load(chunk_src(0), avA);
 #pragma unroll
-  for (int ct = 0; ct < CT; ++ct) w0[ct] = st.w0[ct];
+  for (int ct = 0; ct < CT; ++ct) we[ct] = st.w0[ct];
+  // four steps (two chunks) per iteration
   int s = 0;
-  for (; s + 1 < steps; s += 2) {
-    load(src + 2, av1);
-    weights(w1);
-    contract(av0, w0);
-    order();
-    src = arow + (((((s + 2) >> 1) & 15) << 2) ^ swz4);
-    load(src, av0);
-    weights(w0);
-    contract(av1, w1);
-    order();
+  for (; s + 3 < steps; s += 4) {
+    const int k = s >> 1;
+    load(chunk_src(k + 1), avB);
+    weight_odd();
+    contract(avA, false, we);
+    order(true);
+    weight_even_next();
+    contract(avA, true, wo);
+    order(false);
+    load(chunk_src(k + 2), avA);
+    weight_odd();
+    contract(avB, false, we);
+    order(true);
+    weight_even_next();
+    contract(avB, true, wo);
+    order(false);
   }
-  if (s < steps) contract(av0, w0);
+  // the last 1 to 3 steps: a whole chunk (its successor's samples then move
+  // into the first operand set), then a last even step
+  if (s + 1 < steps) {
+    load(chunk_src((s >> 1) + 1), avB);
+    weight_odd();
+    contract(avA, false, we);
+    order(true);
+    weight_even_next();
+    contract(avA, true, wo);
+    order(false);
+#pragma unroll
+    for (int ft = 0; ft < FT; ++ft) avA[ft] = avB[ft];
+    s += 2;
+  }
+  if (s < steps) contract(avA, false, we);
 }
 
 // COMP: two-level summation for long sample sets. The matrix-core
