@@ -23,7 +23,9 @@
 // FP32 kernel layout (v_mfma_f32_32x32x2f32, D[frame][cand] += A[frame][k] B[k][cand]):
 //   block = NW waves (8; 4 for the two-level sum), two per SIMD; each wave owns
 //   32 * CT candidates, all waves share the block's 32 * FT frames;
-//   step s of a lag run covers lags t = 2s (k = 0, lanes 0-31) and 2s + 1 (k = 1, lanes 32-63);
+//   step s of a lag run covers, of its 4-lag chunk s >> 1, lags 4 (s >> 1) + (s & 1)
+//   (k = 0, lanes 0-31) and 4 (s >> 1) + 2 + (s & 1) (k = 1, lanes 32-63), so a lane
+//   reads the two lags it takes from a chunk with one 8-byte LDS read;
 //   A = samples staged in LDS as [frame][lag]; B = weights (lane = candidate);
 //   epilogue: x2, optional map store, argmax via LDS u64 max + one global atomic per frame.
 #include <type_traits>
