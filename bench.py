@@ -34,6 +34,13 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_TFLOPS = 157.3   # MI355X dense FP32 (matrix cores), published
 PEAK_BF16_TFLOPS = 2500.0  # MI355X dense BF16 / FP16 (matrix cores), published
 PEAK_HBM_GBS = 8000.0
+# Weight-generation bound of the BF16/FP16 map kernel: its non-matrix vector
+# instructions per sinc weight and lane, (SQ_INSTS_VALU - SQ_INSTS_MFMA) x 64
+# over J S ceil(F / 256) weights, from the SQ counters at the room scale
+# ((1.037e9 - 1.334e8) x 64 / (576,000 x 6,544 x 2); the per-run TDOA split and
+# staging included), issued at one wave64 instruction per 4 cycles per SIMD.
+MX_VALU_PER_WEIGHT = 7.67
+VALU_ISSUE_WAVE_INSTR_PER_S = 1024 * 2.4e9 / 4
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_nyquist_f32_cfg2.json")
 
 
@@ -434,6 +441,18 @@ def _timed(step, steps: int, n_marks: int):
     return ms, gaps
 
 
+def weight_bound(J: int, S: int, F: int, map_ms: float) -> dict:
+    """Time the BF16/FP16 map's weight arithmetic alone would take: one set of
+    sinc weights per (candidate, sample) and 256-frame block, at the measured
+    vector instructions per weight and the SIMDs' issue rate (published clock)."""
+    w = J * S * -(-F // 256)
+    ms = w * MX_VALU_PER_WEIGHT / 64 / VALU_ISSUE_WAVE_INSTR_PER_S * 1e3
+    return {"weights_per_call": w, "valu_lane_instr_per_weight": MX_VALU_PER_WEIGHT,
+            "valu_issue_wave_instr_per_s": VALU_ISSUE_WAVE_INSTR_PER_S, "ms": ms,
+            "frac_of_map_time": ms / map_ms,
+            "per_weight_count_from": "SQ counters, room scale"}
+
+
 def _dist_to_source(wl, idx):
     """Median over frames of the distance (m) from the picked candidate to the
     nearest true source."""
@@ -473,15 +492,16 @@ def other_geometry_leg(srp, torch, cfg: int, dtypes, steps: dict, F=None):
         peaks[dt] = idx
         ach = flops / (t_map * 1e-3) / 1e12
         peak = PEAK_FP32_TFLOPS if dt == "fp32" else PEAK_BF16_TFLOPS
-        # weight pairs generated per second: one (candidate, pair) pair of sinc
-        # weights per 256-frame tile (BF16/FP16) or per 8-frame tile (FP32)
-        tile = 8 if dt == "fp32" else 256
-        wp = wl.J * wl.P * (-(-wl.F // tile))
+        # weight sets formed per second: one (candidate, pair) set of sinc
+        # weights per frame block of up to 256 frames (both kernels)
+        wp = wl.J * wl.P * (-(-wl.F // 256))
         res[dt] = {"steps": steps[dt], "ms_per_step": ms, "map_kernel_ms": t_map,
                    "value": wl.F * wl.J * wl.P / (ms * 1e-3), "unit": "cand-pair evals/s",
                    "achieved_tflops": ach, "peak_tflops": peak, "frac": ach / peak,
                    "weight_pairs_per_s": wp / (t_map * 1e-3),
                    "median_dist_to_source_m": _dist_to_source(wl, idx)}
+        if dt != "fp32":
+            res[dt]["weight_bound"] = weight_bound(wl.J, g.W_total, wl.F, t_map)
         print(f"[bench] {wl.name} nyquist {dt}: {ms:.1f} ms/step (map {t_map:.1f} ms, "
               f"{ach:.0f} TFLOP/s)", file=sys.stderr, flush=True)
     for a in dtypes:
@@ -653,7 +673,8 @@ def main():
             "map_kernel_ms": t_map_l, "front_end_ms": t_front_l, "achieved_tflops": ach,
             "peak_tflops": PEAK_BF16_TFLOPS,
             "frac": ach / PEAK_BF16_TFLOPS, "speedup_vs_fp32": ms_step / ms_l,
-            "argmax_agree_with_fp32": float(np.mean(pk_l == ref_pk))}
+            "argmax_agree_with_fp32": float(np.mean(pk_l == ref_pk)),
+            "weight_bound": weight_bound(wl.J, NP, wl.F, t_map_l)}
         print(f"[bench] nyquist {dt}: {ms_l:.3f} ms/step (map {t_map_l:.3f} ms, {ach:.0f} TFLOP/s)",
               file=sys.stderr, flush=True)
 
