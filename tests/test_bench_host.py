@@ -43,3 +43,16 @@ def test_traffic_reported_only_for_its_source_and_workload(tmp_path, monkeypatch
 def test_traffic_missing_file_is_none(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "absent.json"))
     assert bench.load_traffic("room") is None
+
+
+def test_weight_bound_counts_one_weight_set_per_256_frame_block():
+    # 576,000 candidates x 6,544 samples per frame x 2 frame blocks (500 frames)
+    b = bench.weight_bound(576000, 6544, 500, 4.0)
+    assert b["weights_per_call"] == 576000 * 6544 * 2
+    # the time is weights x instructions per weight / 64 lanes / issue rate
+    ms = 576000 * 6544 * 2 * bench.MX_VALU_PER_WEIGHT / 64 / (1024 * 2.4e9 / 4) * 1e3
+    assert b["ms"] == pytest.approx(ms, rel=1e-12)
+    assert b["frac_of_map_time"] == pytest.approx(ms / 4.0, rel=1e-12)
+    # 256 frames still fit one block; 257 need two
+    assert bench.weight_bound(10, 10, 256, 1.0)["weights_per_call"] == 100
+    assert bench.weight_bound(10, 10, 257, 1.0)["weights_per_call"] == 200
