@@ -417,11 +417,30 @@ void nyquist_mx2_kernel(MxArgs a, const T* __restrict__ xi, const RunRec* __rest
     // round (the run count is even)
     const RunRec r0 = recs[ri];
     const RunRec r1 = recs[ri + 1];
+    // Every record field this iteration reads, the next run's staging fields
+    // included, is tied to a scalar register here, so their scalar loads issue
+    // together and wait once, not once per first use inside the runs (a wait
+    // that stalls the matrix-core stream of the wave).
+    auto pin = [](const RunRec& r) __attribute__((always_inline)) {
+      asm volatile("" ::"s"(r.p), "s"(r.t0), "s"(r.len), "s"(r.off), "s"(r.h), "s"(r.m));
+      asm volatile("" ::"s"(r.pm[0]), "s"(r.pm[1]), "s"(r.pm[2]));
+      asm volatile("" ::"s"(r.pn[0]), "s"(r.pn[1]), "s"(r.pn[2]));
+    };
+    pin(r0);
+    pin(r1);
+    RunRec r2;
+    {
+      const RunRec& nx = recs[ri + 2 < a.n_runs ? ri + 2 : ri];
+      r2.t0 = nx.t0;
+      r2.len = nx.len;
+      r2.off = nx.off;
+      asm volatile("" ::"s"(r2.t0), "s"(r2.len), "s"(r2.off));
+    }
     stage(r1, xs1);
     contract_run(r0, xs0);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (ri + 2 < a.n_runs) stage(recs[ri + 2], xs0);
+    if (ri + 2 < a.n_runs) stage(r2, xs0);  // (reads t0, len and off only)
     contract_run(r1, xs1);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
