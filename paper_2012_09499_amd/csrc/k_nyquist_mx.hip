@@ -12,7 +12,7 @@
 // tile (A = samples, one 16-byte LDS read per tile) and for candidate cl
 // (B = weights, formed in registers).
 //
-// Samples. Each lag run (<= 64 lags of one pair window, lagrun records of the
+// Samples. Each lag run (<= 128 lags of one pair window, lagrun records of the
 // geometry) is copied into LDS with 16-byte global-to-LDS copies issued by all
 // waves, double-buffered: the next run's copies are in flight while the
 // current run is contracted. For each pair of 16-byte chunks and each group of
@@ -136,7 +136,10 @@ void nyquist_mx2_kernel(MxArgs a, const T* __restrict__ xi, const RunRec* __rest
   constexpr int FB = 32 * FT;
   constexpr int JW = 32 * CT;            // candidates per wave
   constexpr int JB = JW * NW;
-  constexpr int kTile = 4 * FB * 16;     // elements of a staging tile (4 chunk pairs)
+  // chunk pairs (16 lags or 8 bins) of a staging tile: a Nyquist lag run
+  // (<= kMxRunMax lags) or a conventional 32-bin run
+  constexpr int kChunkPairs = CONV ? 4 : kMxRunMax / 16;
+  constexpr int kTile = kChunkPairs * FB * 16;  // elements of a staging tile
   __shared__ __attribute__((aligned(16))) T xs0[kTile];
   __shared__ __attribute__((aligned(16))) T xs1[kTile];
   __shared__ unsigned long long kbest[FB];
@@ -194,7 +197,7 @@ void nyquist_mx2_kernel(MxArgs a, const T* __restrict__ xi, const RunRec* __rest
     const int npairs = (nch + 1) >> 1;
     const char* base = reinterpret_cast<const char*>(xblk + run.off + run.t0);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < kChunkPairs; ++j) {
       if (j >= npairs) break;  // (uniform)
       const int ch = 2 * j + sub < nch ? 2 * j + sub : nch - 1;
 #pragma unroll
@@ -548,7 +551,7 @@ hipError_t launch_nyquist_mx2(const srp_geometry_s* g, const void* xi, int F, in
   a.j_base = 0;
   a.S = static_cast<int>(g->info.S);
   a.J = g->info.J;
-  a.n_runs = static_cast<int>(g->nyq_runs.size());
+  a.n_runs = static_cast<int>(g->mx_runs.size());
   a.inv_cT = g->inv_cT;
   a.xq_scale = std::ldexp(1.0, mx_fraction_grid_exponent(g->info.h_max));
   a.xq_inv = std::ldexp(1.0, -mx_fraction_grid_exponent(g->info.h_max));
@@ -562,10 +565,10 @@ hipError_t launch_nyquist_mx2(const srp_geometry_s* g, const void* xi, int F, in
     const dim3 blk(64 * kWavesPerBlock);
     if (dtype == SRP_BF16)
       hipLaunchKernelGGL((nyquist_mx2_kernel<__bf16, FTv, kTiles, kWavesPerBlock, false>), grid,
-                         blk, 0, s, b, static_cast<const __bf16*>(xi), g->d_nyq_recs);
+                         blk, 0, s, b, static_cast<const __bf16*>(xi), g->d_mx_recs);
     else
       hipLaunchKernelGGL((nyquist_mx2_kernel<_Float16, FTv, kTiles, kWavesPerBlock, false>),
-                         grid, blk, 0, s, b, static_cast<const _Float16*>(xi), g->d_nyq_recs);
+                         grid, blk, 0, s, b, static_cast<const _Float16*>(xi), g->d_mx_recs);
   });
   return hipGetLastError();
 }

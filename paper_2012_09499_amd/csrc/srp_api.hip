@@ -104,6 +104,7 @@ void free_geometry(srp_geometry_s* g) {
   hipFree(g->d_gcc_items);
   hipFree(g->d_nyq_runs);
   hipFree(g->d_nyq_recs);
+  hipFree(g->d_mx_recs);
   hipFree(g->d_convmx_recs);
   hipFree(g->d_conv_runs);
   hipFree(g->d_window);
@@ -230,17 +231,24 @@ srp_status srp_geometry(const double* mic_xyz, int32_t M, const double* cand_xyz
     // on an aligned column), not into full runs and a short remainder: each
     // run costs a fixed copy and synchronisation, which a short run does not
     // cover with work
-    const int nr = (W + kNyqRunMax - 1) / kNyqRunMax;
-    const int per = (W + nr - 1) / nr;
-    const int run_len = (per + kSampleAlign - 1) / kSampleAlign * kSampleAlign;
-    for (int t0 = 0; t0 < W; t0 += run_len)
-      g->nyq_runs.push_back(LagRun{p, t0, W - t0 < run_len ? W - t0 : run_len, 0});
+    auto split = [&](int run_max, std::vector<LagRun>& runs) {
+      const int nr = (W + run_max - 1) / run_max;
+      const int per = (W + nr - 1) / nr;
+      const int run_len = (per + kSampleAlign - 1) / kSampleAlign * kSampleAlign;
+      for (int t0 = 0; t0 < W; t0 += run_len)
+        runs.push_back(LagRun{p, t0, W - t0 < run_len ? W - t0 : run_len, 0});
+    };
+    split(kNyqRunMax, g->nyq_runs);
+    split(kMxRunMax, g->mx_runs);
   }
   // the FP32 interpolation kernel consumes runs two at a time, the BF16/FP16
   // one three at a time: pad to a multiple of 6 with empty runs of the last
   // pair (no lags, no copy, no pair change)
   while (g->nyq_runs.size() % 6)
     g->nyq_runs.push_back(LagRun{P - 1, 2 * (np[P - 1] + n_aux) + 1, 0, 0});
+  // the BF16/FP16 kernel consumes its runs two at a time
+  if (g->mx_runs.size() % 2)
+    g->mx_runs.push_back(LagRun{P - 1, 2 * (np[P - 1] + n_aux) + 1, 0, 0});
   // the fused GCC kernel deals its units out largest first
   std::stable_sort(g->gcc_items.begin(), g->gcc_items.end(),
                    [](const GccItem& a, const GccItem& b) { return a.nt > b.nt; });
@@ -315,25 +323,33 @@ srp_status srp_geometry(const double* mic_xyz, int32_t M, const double* cand_xyz
   if (e == hipSuccess) e = upload(&g->d_gcc_tiles, g->gcc_tiles.data(), g->gcc_tiles.size(), s);
   if (e == hipSuccess) e = upload(&g->d_gcc_items, g->gcc_items.data(), g->gcc_items.size(), s);
   if (e == hipSuccess) e = upload(&g->d_nyq_runs, g->nyq_runs.data(), g->nyq_runs.size(), s);
-  std::vector<RunRec> recs(g->nyq_runs.size());
-  for (size_t i = 0; i < recs.size(); ++i) {
-    const LagRun& r = g->nyq_runs[i];
-    const PairDesc& pd = g->pairs[r.p];
-    RunRec& q = recs[i];
-    q.p = r.p;
-    q.t0 = r.t0;
-    q.len = r.len;
-    q.off = pd.off;
-    q.h = pd.h;
-    q.m = pd.m;
-    q.mp = pd.mp;
-    q.pad = 0;
-    for (int d = 0; d < 3; ++d) {
-      q.pm[d] = mic_xyz[3 * pd.m + d];
-      q.pn[d] = mic_xyz[3 * pd.mp + d];
+  // self-contained records of the lag runs (the run, its pair's window and
+  // microphone positions) for the kernels that read one record per run
+  auto run_records = [&](const std::vector<LagRun>& runs) {
+    std::vector<RunRec> recs(runs.size());
+    for (size_t i = 0; i < recs.size(); ++i) {
+      const LagRun& r = runs[i];
+      const PairDesc& pd = g->pairs[r.p];
+      RunRec& q = recs[i];
+      q.p = r.p;
+      q.t0 = r.t0;
+      q.len = r.len;
+      q.off = pd.off;
+      q.h = pd.h;
+      q.m = pd.m;
+      q.mp = pd.mp;
+      q.pad = 0;
+      for (int d = 0; d < 3; ++d) {
+        q.pm[d] = mic_xyz[3 * pd.m + d];
+        q.pn[d] = mic_xyz[3 * pd.mp + d];
+      }
     }
-  }
+    return recs;
+  };
+  const std::vector<RunRec> recs = run_records(g->nyq_runs);
+  const std::vector<RunRec> mx_recs = run_records(g->mx_runs);
   if (e == hipSuccess) e = upload(&g->d_nyq_recs, recs.data(), recs.size(), s);
+  if (e == hipSuccess) e = upload(&g->d_mx_recs, mx_recs.data(), mx_recs.size(), s);
   // 32-bin runs of the BF16/FP16 conventional map over the weighted spectra
   // [F][P][Kp] x (re, im): a run's values start at 2 (p Kp + k0) of a frame row
   g->Kp = (in.K + 7) / 8 * 8;

@@ -37,6 +37,11 @@ struct RunRec {
 // Lag runs of the Nyquist interpolation kernels are at most this long (one
 // lane per lag when a wave copies a run into LDS).
 constexpr int kNyqRunMax = 64;
+// Lag runs of the BF16/FP16 Nyquist kernel are at most this long (8 of its
+// 16-lag steps): one run per pair window up to 128 lags, so fewer run
+// boundaries (a copy, a barrier and a pipeline restart each) than with
+// kNyqRunMax.
+constexpr int kMxRunMax = 128;
 // Pair windows of the GCC-sample layout start at multiples of this many
 // samples (16 bytes of bf16/fp16), so staging copies can move 16-byte chunks.
 constexpr int kSampleAlign = 8;
@@ -98,6 +103,7 @@ struct srp_geometry_s {
   std::vector<srp::LagRun> gcc_tiles;  // lag tiles of srp_gcc_samples
   std::vector<srp::GccItem> gcc_items;  // workgroup items of srp_gcc_samples_frames
   std::vector<srp::LagRun> nyq_runs;   // lag runs of srp_map_nyquist (even count)
+  std::vector<srp::LagRun> mx_runs;    // lag runs of the BF16/FP16 Nyquist map (even count)
   std::vector<srp::LagRun> conv_runs;  // bin runs (p, k0, len) of srp_map_conventional (even count)
   // device copies
   double* d_mic = nullptr;             // [M][3]
@@ -107,6 +113,7 @@ struct srp_geometry_s {
   srp::GccItem* d_gcc_items = nullptr;
   srp::LagRun* d_nyq_runs = nullptr;
   srp::RunRec* d_nyq_recs = nullptr;   // one record per entry of nyq_runs
+  srp::RunRec* d_mx_recs = nullptr;    // one record per entry of mx_runs
   srp::RunRec* d_convmx_recs = nullptr;  // 32-bin runs of the BF16/FP16 conventional map
   srp::LagRun* d_conv_runs = nullptr;
   float* d_window = nullptr;           // [L]
