@@ -37,9 +37,9 @@ PEAK_HBM_GBS = 8000.0
 # Weight-generation bound of the BF16/FP16 map kernel: its non-matrix vector
 # instructions per sinc weight and lane, (SQ_INSTS_VALU - SQ_INSTS_MFMA) x 64
 # over J S ceil(F / 256) weights, from the SQ counters at the room scale
-# ((1.005e9 - 1.298e8) x 64 / (576,000 x 6,544 x 2); the per-run TDOA split and
+# ((9.751e8 - 1.298e8) x 64 / (576,000 x 6,544 x 2); the per-run TDOA split and
 # staging included), issued at one wave64 instruction per 4 cycles per SIMD.
-MX_VALU_PER_WEIGHT = 7.43
+MX_VALU_PER_WEIGHT = 7.18
 VALU_ISSUE_WAVE_INSTR_PER_S = 1024 * 2.4e9 / 4
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_nyquist_f32_cfg2.json")
 

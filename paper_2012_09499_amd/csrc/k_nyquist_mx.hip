@@ -31,7 +31,10 @@
 // denominators a pair of weights costs one fma for d (d - 1), one reciprocal
 // and three multiplies: with u = d_j, r = qs / (u (u - 1)),
 // w_j = (u - 1) r and w_{j+1} = -u r, qs = (-1)^(xi - n) sin(pi xf) / pi.
-// TDOAs are float64 per pair as in every map kernel.
+// TDOAs are float32 per pair, from float32 candidate and microphone positions:
+// their error, about 2^-23 of the largest distance times 2 fs / c (1e-4
+// samples at 10 m and 48 kHz), stays below the BF16/FP16 rounding of the
+// weights (the conventional path computes them in float64).
 #include <cmath>
 #include <type_traits>
 #include <utility>
@@ -224,11 +227,61 @@ void nyquist_mx2_kernel(MxArgs a, const T* __restrict__ xi, const RunRec* __rest
   // conventional map the TDOA in samples and the phasors of 1 and 8 bins
   int cur_p = -1, cur_m = -1;
   double rm = 0.0;
+  float rmf = 0.0f;
   int xr[CT];
   float xf[CT], sp[CT];
   double xs = 0.0;
   float r1c = 1.0f, r1s = 0.0f, r8c = 1.0f, r8s = 0.0f;
+  // Nyquist: the TDOA and its split in float32, from the candidate and the
+  // microphone positions rounded to float32: an error of about 2^-23 of the
+  // largest distance, times 2 fs / c (1e-4 samples at 10 m and 48 kHz), below
+  // the BF16/FP16 rounding of the weights it moves
+  const float qxf = static_cast<float>(qx), qyf = static_cast<float>(qy),
+              qzf = static_cast<float>(qz);
+  const float inv_cT_f = static_cast<float>(a.inv_cT);
+  const float xq_scale_f = static_cast<float>(a.xq_scale);
+  const float xq_inv_f = static_cast<float>(a.xq_inv);
+  auto norm3f = [](float dx, float dy, float dz) __attribute__((always_inline)) {
+    return __builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+  };
   auto pair_split = [&](const RunRec& run) __attribute__((always_inline)) {
+    if constexpr (!CONV) {
+      float x;
+      if (a.far_field) {
+        x = ((run.pmf[0] - run.pnf[0]) * qxf + (run.pmf[1] - run.pnf[1]) * qyf +
+             (run.pmf[2] - run.pnf[2]) * qzf) * inv_cT_f;
+      } else {
+        if (run.m != cur_m) {
+          rmf = norm3f(qxf - run.pmf[0], qyf - run.pmf[1], qzf - run.pmf[2]);
+          cur_m = run.m;
+        }
+        x = (rmf - norm3f(qxf - run.pnf[0], qyf - run.pnf[1], qzf - run.pnf[2])) * inv_cT_f;
+      }
+      const float r = rintf(x);
+      const float fd0 = x - r;  // exact
+      float q = rintf(fd0 * xq_scale_f);
+      q = q != 0.0f ? q : (fd0 < 0.0f ? -1.0f : 1.0f);
+      const float fd = q * xq_inv_f;  // exact (a power of two)
+      const int xr_own = static_cast<int>(r);
+      const float sp_own = sinpi_over_pi_f32(fd);
+      if (CT == 2) {
+        const int xr_oth = __shfl_xor(xr_own, 32, 64);
+        const float xf_oth = __shfl_xor(fd, 32, 64);
+        const float sp_oth = __shfl_xor(sp_own, 32, 64);
+        xr[0] = g ? xr_oth : xr_own;
+        xr[CT - 1] = g ? xr_own : xr_oth;
+        xf[0] = g ? xf_oth : fd;
+        xf[CT - 1] = g ? fd : xf_oth;
+        sp[0] = g ? sp_oth : sp_own;
+        sp[CT - 1] = g ? sp_own : sp_oth;
+      } else {
+        xr[0] = xr_own;
+        xf[0] = fd;
+        sp[0] = sp_own;
+      }
+      cur_p = run.p;
+      return;
+    }
     double x;
     if (a.far_field) {
       x = ((run.pm[0] - run.pn[0]) * qx + (run.pm[1] - run.pn[1]) * qy +
@@ -240,39 +293,12 @@ void nyquist_mx2_kernel(MxArgs a, const T* __restrict__ xi, const RunRec* __rest
       }
       x = (rm - norm3(qx - run.pn[0], qy - run.pn[1], qz - run.pn[2])) * a.inv_cT;
     }
-    if (CONV) {
-      // x is the TDOA in samples; phase of bin k: k x / L turns, reduced mod 1
-      // in float64, then rounded to float32 for the rotations
-      xs = x;
-      const double t1 = x * a.inv_L, t8 = 8.0 * t1;
-      sincospif(2.0f * static_cast<float>(t1 - rint(t1)), &r1s, &r1c);
-      sincospif(2.0f * static_cast<float>(t8 - rint(t8)), &r8s, &r8c);
-      cur_p = run.p;
-      return;
-    }
-    const double r = rint(x);
-    const double fd0 = x - r;
-    double q = rint(fd0 * a.xq_scale);
-    q = q != 0.0 ? q : (fd0 < 0.0 ? -1.0 : 1.0);
-    const double fd = q * a.xq_inv;  // exact (a power of two)
-    const int xr_own = static_cast<int>(r);
-    const float xf_own = static_cast<float>(fd);  // exact: a grid point
-    const float sp_own = sinpi_over_pi_f32(xf_own);
-    if (CT == 2) {
-      const int xr_oth = __shfl_xor(xr_own, 32, 64);
-      const float xf_oth = __shfl_xor(xf_own, 32, 64);
-      const float sp_oth = __shfl_xor(sp_own, 32, 64);
-      xr[0] = g ? xr_oth : xr_own;
-      xr[CT - 1] = g ? xr_own : xr_oth;
-      xf[0] = g ? xf_oth : xf_own;
-      xf[CT - 1] = g ? xf_own : xf_oth;
-      sp[0] = g ? sp_oth : sp_own;
-      sp[CT - 1] = g ? sp_own : sp_oth;
-    } else {
-      xr[0] = xr_own;
-      xf[0] = xf_own;
-      sp[0] = sp_own;
-    }
+    // conventional: x is the TDOA in samples; phase of bin k: k x / L turns,
+    // reduced mod 1 in float64, then rounded to float32 for the rotations
+    xs = x;
+    const double t1 = x * a.inv_L, t8 = 8.0 * t1;
+    sincospif(2.0f * static_cast<float>(t1 - rint(t1)), &r1s, &r1c);
+    sincospif(2.0f * static_cast<float>(t8 - rint(t8)), &r8s, &r8c);
     cur_p = run.p;
   };
 
@@ -426,8 +452,13 @@ void nyquist_mx2_kernel(MxArgs a, const T* __restrict__ xi, const RunRec* __rest
     // that stalls the matrix-core stream of the wave).
     auto pin = [](const RunRec& r) __attribute__((always_inline)) {
       asm volatile("" ::"s"(r.p), "s"(r.t0), "s"(r.len), "s"(r.off), "s"(r.h), "s"(r.m));
-      asm volatile("" ::"s"(r.pm[0]), "s"(r.pm[1]), "s"(r.pm[2]));
-      asm volatile("" ::"s"(r.pn[0]), "s"(r.pn[1]), "s"(r.pn[2]));
+      if constexpr (CONV) {
+        asm volatile("" ::"s"(r.pm[0]), "s"(r.pm[1]), "s"(r.pm[2]));
+        asm volatile("" ::"s"(r.pn[0]), "s"(r.pn[1]), "s"(r.pn[2]));
+      } else {
+        asm volatile("" ::"s"(r.pmf[0]), "s"(r.pmf[1]), "s"(r.pmf[2]));
+        asm volatile("" ::"s"(r.pnf[0]), "s"(r.pnf[1]), "s"(r.pnf[2]));
+      }
     };
     pin(r0);
     pin(r1);

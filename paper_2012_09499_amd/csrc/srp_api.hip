@@ -342,6 +342,8 @@ srp_status srp_geometry(const double* mic_xyz, int32_t M, const double* cand_xyz
       for (int d = 0; d < 3; ++d) {
         q.pm[d] = mic_xyz[3 * pd.m + d];
         q.pn[d] = mic_xyz[3 * pd.mp + d];
+        q.pmf[d] = static_cast<float>(q.pm[d]);
+        q.pnf[d] = static_cast<float>(q.pn[d]);
       }
     }
     return recs;
@@ -369,6 +371,8 @@ srp_status srp_geometry(const double* mic_xyz, int32_t M, const double* cand_xyz
       for (int d = 0; d < 3; ++d) {
         q.pm[d] = mic_xyz[3 * pd.m + d];
         q.pn[d] = mic_xyz[3 * pd.mp + d];
+        q.pmf[d] = static_cast<float>(q.pm[d]);
+        q.pnf[d] = static_cast<float>(q.pn[d]);
       }
       crecs.push_back(q);
     }

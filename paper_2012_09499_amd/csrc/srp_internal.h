@@ -32,6 +32,7 @@ struct RunRec {
   int32_t p, t0, len, off;  // the run, and its pair's window offset in the sample layout
   int32_t h, m, mp, pad;    // the pair: half window, microphones m > mp
   double pm[3], pn[3];      // positions of microphones m and mp
+  float pmf[3], pnf[3];     // the same rounded to float32 (the Nyquist BF16/FP16 TDOAs)
 };
 
 // Lag runs of the Nyquist interpolation kernels are at most this long (one
