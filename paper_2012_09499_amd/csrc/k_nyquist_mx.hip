@@ -31,10 +31,11 @@
 // denominators a pair of weights costs one fma for d (d - 1), one reciprocal
 // and three multiplies: with u = d_j, r = qs / (u (u - 1)),
 // w_j = (u - 1) r and w_{j+1} = -u r, qs = (-1)^(xi - n) sin(pi xf) / pi.
-// TDOAs are float32 per pair, from float32 candidate and microphone positions:
-// their error, about 2^-23 of the largest distance times 2 fs / c (1e-4
-// samples at 10 m and 48 kHz), stays below the BF16/FP16 rounding of the
-// weights (the conventional path computes them in float64).
+// TDOAs are float32 per pair, from float32 candidate and microphone positions
+// relative to the microphone centroid: their error, about 2^-23 of the largest
+// candidate-to-array distance times 2 fs / c (1e-4 samples at 10 m and
+// 48 kHz), stays below the BF16/FP16 rounding of the weights (the
+// conventional path computes them in float64).
 #include <cmath>
 #include <type_traits>
 #include <utility>
@@ -91,6 +92,7 @@ struct MxArgs {
   double xq_inv;           // 2^-e
   double inv_L;            // conventional map: 1 / L (bin k has phase k x fs / L turns)
   int far_field;
+  double centre[3];        // origin of the float32 positions (the microphone centroid, near field)
   float* map;              // [F][J] or null
   unsigned long long* keys;  // peaks viewed as u64 pairs, or null
 };
@@ -233,11 +235,13 @@ void nyquist_mx2_kernel(MxArgs a, const T* __restrict__ xi, const RunRec* __rest
   double xs = 0.0;
   float r1c = 1.0f, r1s = 0.0f, r8c = 1.0f, r8s = 0.0f;
   // Nyquist: the TDOA and its split in float32, from the candidate and the
-  // microphone positions rounded to float32: an error of about 2^-23 of the
-  // largest distance, times 2 fs / c (1e-4 samples at 10 m and 48 kHz), below
-  // the BF16/FP16 rounding of the weights it moves
-  const float qxf = static_cast<float>(qx), qyf = static_cast<float>(qy),
-              qzf = static_cast<float>(qz);
+  // microphone positions relative to the microphone centroid, rounded to
+  // float32: an error of about 2^-23 of the largest candidate-to-array
+  // distance, times 2 fs / c (1e-4 samples at 10 m and 48 kHz), below the
+  // BF16/FP16 rounding of the weights it moves
+  const float qxf = static_cast<float>(qx - a.centre[0]),
+              qyf = static_cast<float>(qy - a.centre[1]),
+              qzf = static_cast<float>(qz - a.centre[2]);
   const float inv_cT_f = static_cast<float>(a.inv_cT);
   const float xq_scale_f = static_cast<float>(a.xq_scale);
   const float xq_inv_f = static_cast<float>(a.xq_inv);
@@ -588,6 +592,7 @@ hipError_t launch_nyquist_mx2(const srp_geometry_s* g, const void* xi, int F, in
   a.xq_inv = std::ldexp(1.0, -mx_fraction_grid_exponent(g->info.h_max));
   a.inv_L = 1.0 / g->info.L;
   a.far_field = g->info.field == SRP_FAR_FIELD;
+  for (int d = 0; d < 3; ++d) a.centre[d] = g->mic_centre[d];
   a.map = map;
   a.keys = keys;
   const int per_cu = g->wg_per_cu[dtype == SRP_BF16 ? 1 : 2];
@@ -639,6 +644,7 @@ hipError_t launch_conventional_mx(const srp_geometry_s* g, const void* spec, int
   a.xq_inv = 1.0;
   a.inv_L = 1.0 / g->info.L;
   a.far_field = g->info.field == SRP_FAR_FIELD;
+  for (int d = 0; d < 3; ++d) a.centre[d] = 0.0;  // (float64 positions only)
   a.map = map;
   a.keys = keys;
   const int per_cu = g->wg_per_cu_conv[dtype == SRP_BF16 ? 0 : 1];

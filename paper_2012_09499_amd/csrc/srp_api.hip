@@ -201,6 +201,10 @@ srp_status srp_geometry(const double* mic_xyz, int32_t M, const double* cand_xyz
   in.T = 1.0 / (2.0 * f_max);
   g->inv_cT = 1.0 / (c * in.T);
   g->fs_over_c = fs / c;
+  if (field != SRP_FAR_FIELD) {
+    for (int i = 0; i < M; ++i)
+      for (int d = 0; d < 3; ++d) g->mic_centre[d] += mic_xyz[3 * i + d] / M;
+  }
   g->log2L = 0;
   while ((1 << g->log2L) < L) ++g->log2L;
   g->N_p = np;
@@ -342,8 +346,8 @@ srp_status srp_geometry(const double* mic_xyz, int32_t M, const double* cand_xyz
       for (int d = 0; d < 3; ++d) {
         q.pm[d] = mic_xyz[3 * pd.m + d];
         q.pn[d] = mic_xyz[3 * pd.mp + d];
-        q.pmf[d] = static_cast<float>(q.pm[d]);
-        q.pnf[d] = static_cast<float>(q.pn[d]);
+        q.pmf[d] = static_cast<float>(q.pm[d] - g->mic_centre[d]);
+        q.pnf[d] = static_cast<float>(q.pn[d] - g->mic_centre[d]);
       }
     }
     return recs;
@@ -371,8 +375,8 @@ srp_status srp_geometry(const double* mic_xyz, int32_t M, const double* cand_xyz
       for (int d = 0; d < 3; ++d) {
         q.pm[d] = mic_xyz[3 * pd.m + d];
         q.pn[d] = mic_xyz[3 * pd.mp + d];
-        q.pmf[d] = static_cast<float>(q.pm[d]);
-        q.pnf[d] = static_cast<float>(q.pn[d]);
+        q.pmf[d] = static_cast<float>(q.pm[d] - g->mic_centre[d]);
+        q.pnf[d] = static_cast<float>(q.pn[d] - g->mic_centre[d]);
       }
       crecs.push_back(q);
     }

@@ -32,7 +32,8 @@ struct RunRec {
   int32_t p, t0, len, off;  // the run, and its pair's window offset in the sample layout
   int32_t h, m, mp, pad;    // the pair: half window, microphones m > mp
   double pm[3], pn[3];      // positions of microphones m and mp
-  float pmf[3], pnf[3];     // the same rounded to float32 (the Nyquist BF16/FP16 TDOAs)
+  float pmf[3], pnf[3];     // the same minus the microphone centroid, in float32 (the
+                            // Nyquist BF16/FP16 TDOAs; far field: not shifted)
 };
 
 // Lag runs of the Nyquist interpolation kernels are at most this long (one
@@ -96,6 +97,7 @@ struct srp_geometry_s {
   int n_convmx_runs = 0;   // 32-bin runs of the BF16/FP16 conventional map (even count)
   double inv_cT = 0.0;     // converts a path difference in metres into x = dt / T
   double fs_over_c = 0.0;  // converts a path difference in metres into samples
+  double mic_centre[3] = {0.0, 0.0, 0.0};  // centroid of the microphones (near field)
   int log2L = 0;
   int gcc_nw = 0;          // row width of the GCC phase tables (2 h_max + 34, even)
   std::vector<srp::PairDesc> pairs;

@@ -408,6 +408,35 @@ def test_nyquist_lowp_pipeline(cases, name, dtype):
     R.check_argmax(idx, ref, LOWP_TOL, label=f"pipeline-nyquist/{name}/{dtype}")
 
 
+@pytest.mark.parametrize("dtype", ["bf16", "fp16"])
+def test_lowp_map_with_far_origin(dtype):
+    """The BF16/FP16 map of an array and grid placed 1 km from the origin.
+
+    Those kernels take TDOAs in float32 from positions relative to the
+    microphone centroid, so the shift must change nothing beyond rounding:
+    within the low-precision tolerance of the float64 oracle of the shifted
+    geometry, and close to the map of the unshifted one.
+    """
+    wl = WL.make_custom(M=6, J_shape=(9, 7, 5), L=512, F=6, seed=31)
+    shift = np.array([1000.0, -700.0, 300.0])
+    far = WL.Workload(name="far-origin", mic_xyz=wl.mic_xyz + shift, grid=None, fs=wl.fs, L=wl.L,
+                      F=wl.F, c=wl.c, n_aux=wl.n_aux, frames=wl.frames)
+    cand = wl.candidates() + shift
+    maps = []
+    for mic, cq in ((wl.mic_xyz, wl.candidates()), (far.mic_xyz, cand)):
+        g = srp.Geometry(mic, cq, fs=wl.fs, L=wl.L, c=wl.c, n_aux=wl.n_aux)
+        pipe = srp.SrpPipeline(g, wl.F, keep_map=True)
+        m, _ = pipe.nyquist(_frames(wl), dtype=dtype)
+        torch.cuda.synchronize()
+        maps.append(m.cpu().numpy().astype(np.float64))
+        g.close()
+    ref = R.oracle_nyquist(far, R.oracle_xi(far, R.oracle_psi(far)), cand)
+    assert _rel(maps[1], ref).max() <= LOWP_TOL
+    # the two maps differ by the float64 rounding of the shifted coordinates
+    # (and the weight roundings it flips), far below the tolerance
+    assert np.abs(maps[1] - maps[0]).max() <= 2e-3 * np.abs(maps[0]).max()
+
+
 @pytest.mark.parametrize("dtype", ["fp32", "bf16", "fp16"])
 def test_near_integer_tdoa_stays_finite(dtype):
     """TDOAs within 1e-10 .. 1e-7 samples of an integer (|x - rint(x)| tiny but not 0).
