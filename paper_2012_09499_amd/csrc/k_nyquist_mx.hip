@@ -12,8 +12,8 @@
 // tile (A = samples, one 16-byte LDS read per tile) and for candidate cl
 // (B = weights, formed in registers).
 //
-// Samples. Each lag run (<= 128 lags of one pair window, lagrun records of the
-// geometry) is copied into LDS with 16-byte global-to-LDS copies issued by all
+// Samples. Each lag run (<= 128 lags of one pair window, <= 256 with at most
+// 4 frame tiles; lagrun records of the geometry) is copied into LDS with 16-byte global-to-LDS copies issued by all
 // waves, double-buffered: the next run's copies are in flight while the
 // current run is contracted. For each pair of 16-byte chunks and each group of
 // 32 rows, the tile holds the rows' first chunks, then their second chunks, so
@@ -142,8 +142,9 @@ void nyquist_mx2_kernel(MxArgs a, const T* __restrict__ xi, const RunRec* __rest
   constexpr int JW = 32 * CT;            // candidates per wave
   constexpr int JB = JW * NW;
   // chunk pairs (16 lags or 8 bins) of a staging tile: a Nyquist lag run
-  // (<= kMxRunMax lags) or a conventional 32-bin run
-  constexpr int kChunkPairs = CONV ? 4 : kMxRunMax / 16;
+  // (<= kMxRunMax lags, <= kMxRunMaxFew with at most 4 frame tiles) or a
+  // conventional 32-bin run
+  constexpr int kChunkPairs = CONV ? 4 : (FT <= 4 ? kMxRunMaxFew : kMxRunMax) / 16;
   constexpr int kTile = kChunkPairs * FB * 16;  // elements of a staging tile
   __shared__ __attribute__((aligned(16))) T xs0[kTile];
   __shared__ __attribute__((aligned(16))) T xs1[kTile];
@@ -586,7 +587,7 @@ hipError_t launch_nyquist_mx2(const srp_geometry_s* g, const void* xi, int F, in
   a.j_base = 0;
   a.S = static_cast<int>(g->info.S);
   a.J = g->info.J;
-  a.n_runs = static_cast<int>(g->mx_runs.size());
+  a.n_runs = 0;  // per launch: the run list its frame-tile count takes
   a.inv_cT = g->inv_cT;
   a.xq_scale = std::ldexp(1.0, mx_fraction_grid_exponent(g->info.h_max));
   a.xq_inv = std::ldexp(1.0, -mx_fraction_grid_exponent(g->info.h_max));
@@ -598,13 +599,17 @@ hipError_t launch_nyquist_mx2(const srp_geometry_s* g, const void* xi, int F, in
   const int per_cu = g->wg_per_cu[dtype == SRP_BF16 ? 1 : 2];
   launch_in_rounds(g, F, a, per_cu, [&](auto ft, const MxArgs& b, dim3 grid) {
     constexpr int FTv = decltype(ft)::value;
+    constexpr bool kFew = FTv <= 4;  // the kernel's staging tile holds kMxRunMaxFew lags
+    MxArgs c = b;
+    c.n_runs = static_cast<int>((kFew ? g->mx_runs_few : g->mx_runs).size());
+    const RunRec* recs = kFew ? g->d_mx_recs_few : g->d_mx_recs;
     const dim3 blk(64 * kWavesPerBlock);
     if (dtype == SRP_BF16)
       hipLaunchKernelGGL((nyquist_mx2_kernel<__bf16, FTv, kTiles, kWavesPerBlock, false>), grid,
-                         blk, 0, s, b, static_cast<const __bf16*>(xi), g->d_mx_recs);
+                         blk, 0, s, c, static_cast<const __bf16*>(xi), recs);
     else
       hipLaunchKernelGGL((nyquist_mx2_kernel<_Float16, FTv, kTiles, kWavesPerBlock, false>),
-                         grid, blk, 0, s, b, static_cast<const _Float16*>(xi), g->d_mx_recs);
+                         grid, blk, 0, s, c, static_cast<const _Float16*>(xi), recs);
   });
   return hipGetLastError();
 }

@@ -105,6 +105,7 @@ void free_geometry(srp_geometry_s* g) {
   hipFree(g->d_nyq_runs);
   hipFree(g->d_nyq_recs);
   hipFree(g->d_mx_recs);
+  hipFree(g->d_mx_recs_few);
   hipFree(g->d_convmx_recs);
   hipFree(g->d_conv_runs);
   hipFree(g->d_window);
@@ -244,6 +245,7 @@ srp_status srp_geometry(const double* mic_xyz, int32_t M, const double* cand_xyz
     };
     split(kNyqRunMax, g->nyq_runs);
     split(kMxRunMax, g->mx_runs);
+    split(kMxRunMaxFew, g->mx_runs_few);
   }
   // the FP32 interpolation kernel consumes runs two at a time, the BF16/FP16
   // one three at a time: pad to a multiple of 6 with empty runs of the last
@@ -251,8 +253,8 @@ srp_status srp_geometry(const double* mic_xyz, int32_t M, const double* cand_xyz
   while (g->nyq_runs.size() % 6)
     g->nyq_runs.push_back(LagRun{P - 1, 2 * (np[P - 1] + n_aux) + 1, 0, 0});
   // the BF16/FP16 kernel consumes its runs two at a time
-  if (g->mx_runs.size() % 2)
-    g->mx_runs.push_back(LagRun{P - 1, 2 * (np[P - 1] + n_aux) + 1, 0, 0});
+  for (std::vector<LagRun>* runs : {&g->mx_runs, &g->mx_runs_few})
+    if (runs->size() % 2) runs->push_back(LagRun{P - 1, 2 * (np[P - 1] + n_aux) + 1, 0, 0});
   // the fused GCC kernel deals its units out largest first
   std::stable_sort(g->gcc_items.begin(), g->gcc_items.end(),
                    [](const GccItem& a, const GccItem& b) { return a.nt > b.nt; });
@@ -354,8 +356,11 @@ srp_status srp_geometry(const double* mic_xyz, int32_t M, const double* cand_xyz
   };
   const std::vector<RunRec> recs = run_records(g->nyq_runs);
   const std::vector<RunRec> mx_recs = run_records(g->mx_runs);
+  const std::vector<RunRec> mx_recs_few = run_records(g->mx_runs_few);
   if (e == hipSuccess) e = upload(&g->d_nyq_recs, recs.data(), recs.size(), s);
   if (e == hipSuccess) e = upload(&g->d_mx_recs, mx_recs.data(), mx_recs.size(), s);
+  if (e == hipSuccess)
+    e = upload(&g->d_mx_recs_few, mx_recs_few.data(), mx_recs_few.size(), s);
   // 32-bin runs of the BF16/FP16 conventional map over the weighted spectra
   // [F][P][Kp] x (re, im): a run's values start at 2 (p Kp + k0) of a frame row
   g->Kp = (in.K + 7) / 8 * 8;

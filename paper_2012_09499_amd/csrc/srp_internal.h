@@ -44,6 +44,9 @@ constexpr int kNyqRunMax = 64;
 // boundaries (a copy, a barrier and a pipeline restart each) than with
 // kNyqRunMax.
 constexpr int kMxRunMax = 128;
+// ... and at most this long in its launches of at most 4 frame tiles (128
+// frames), whose staging tiles then take the same LDS.
+constexpr int kMxRunMaxFew = 256;
 // Pair windows of the GCC-sample layout start at multiples of this many
 // samples (16 bytes of bf16/fp16), so staging copies can move 16-byte chunks.
 constexpr int kSampleAlign = 8;
@@ -107,6 +110,7 @@ struct srp_geometry_s {
   std::vector<srp::GccItem> gcc_items;  // workgroup items of srp_gcc_samples_frames
   std::vector<srp::LagRun> nyq_runs;   // lag runs of srp_map_nyquist (even count)
   std::vector<srp::LagRun> mx_runs;    // lag runs of the BF16/FP16 Nyquist map (even count)
+  std::vector<srp::LagRun> mx_runs_few;  // the same up to kMxRunMaxFew lags (<= 4 frame tiles)
   std::vector<srp::LagRun> conv_runs;  // bin runs (p, k0, len) of srp_map_conventional (even count)
   // device copies
   double* d_mic = nullptr;             // [M][3]
@@ -117,6 +121,7 @@ struct srp_geometry_s {
   srp::LagRun* d_nyq_runs = nullptr;
   srp::RunRec* d_nyq_recs = nullptr;   // one record per entry of nyq_runs
   srp::RunRec* d_mx_recs = nullptr;    // one record per entry of mx_runs
+  srp::RunRec* d_mx_recs_few = nullptr;  // one record per entry of mx_runs_few
   srp::RunRec* d_convmx_recs = nullptr;  // 32-bin runs of the BF16/FP16 conventional map
   srp::LagRun* d_conv_runs = nullptr;
   float* d_window = nullptr;           // [L]
