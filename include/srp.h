@@ -218,9 +218,12 @@ srp_status srp_map_conventional(const srp_geometry_t* g, const float* psi, int32
 /* Nyquist-Shannon SRP approximation (Eq. SRPapprox summed over pairs as in
  * Eq. SRP_T_IFT; cost Eq. SRPapproxcompR):
  * map[f][i] = 2 sum_p sum_{|n| <= h_p} xi_p(nT) sinc(dt_p(i) / T - n),
- * sinc(x) = sin(pi x) / (pi x), sinc(0) = 1. TDOAs are formed on the fly in
- * float64; sinc weights are formed from the float64 argument split into an
- * integer and a float32 fraction.
+ * sinc(x) = sin(pi x) / (pi x), sinc(0) = 1. TDOAs are formed on the fly:
+ * in float64 for SRP_FP32 and SRP_FP64, whose sinc weights take the float64
+ * argument split into an integer and a float32 fraction; in float32 for
+ * SRP_BF16 and SRP_FP16, from positions relative to the microphone centroid
+ * (an error of about 2^-23 of the largest candidate-to-array distance times
+ * 2 fs / c samples, below the rounding of their weights).
  *   xi     device, F x S samples in the srp_gcc_samples layout, stored as
  *          float for SRP_FP32 and SRP_FP64, bfloat16 for SRP_BF16, half for
  *          SRP_FP16 (srp_gcc_samples with the same dtype writes them); the gap
