@@ -437,6 +437,30 @@ def test_lowp_map_with_far_origin(dtype):
     assert np.abs(maps[1] - maps[0]).max() <= 2e-3 * np.abs(maps[0]).max()
 
 
+@pytest.mark.parametrize("dtype", ["bf16", "fp16"])
+def test_lowp_long_windows_both_run_lists(dtype):
+    """BF16/FP16 Nyquist map with pair windows of 85 .. 447 lags over 260 frames.
+
+    One 256-frame block runs with 8 frame tiles on lag runs of at most 128
+    lags (each window in 1 to 4 runs), the 4-frame tail with one frame tile on
+    runs of at most 256 lags (1 or 2 runs): both run lists of the kernel,
+    against the float64 oracle.
+    """
+    wl = WL.make_custom(M=6, J_shape=(6, 5, 4), h=0.25, fs=48000.0, L=1024, F=260, seed=41,
+                        box=(1.6, 1.4, 0.8))
+    g = _geom(wl)
+    pipe = srp.SrpPipeline(g, wl.F, keep_map=True)
+    m, pk = pipe.nyquist(_frames(wl), dtype=dtype)
+    torch.cuda.synchronize()
+    ref = R.oracle_nyquist(wl, R.oracle_xi(wl, R.oracle_psi(wl)), wl.candidates())
+    got = m.cpu().numpy().astype(np.float64)
+    assert _rel(got, ref).max() <= LOWP_TOL
+    idx = srp.decode_peaks(pk)[0]
+    np.testing.assert_array_equal(idx, np.argmax(got, axis=1))
+    R.check_argmax(idx, ref, LOWP_TOL, label=f"long-windows/{dtype}")
+    g.close()
+
+
 @pytest.mark.parametrize("dtype", ["fp32", "bf16", "fp16"])
 def test_near_integer_tdoa_stays_finite(dtype):
     """TDOAs within 1e-10 .. 1e-7 samples of an integer (|x - rint(x)| tiny but not 0).
